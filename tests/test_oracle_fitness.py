@@ -1,0 +1,98 @@
+"""Pins for the oracle's fitness functions (CPU only): known optima, closed-form
+points and independent library routines (scipy's Rosenbrock, math.fsum)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import rosen
+
+import oracle
+
+
+@pytest.mark.parametrize("D", [1, 10, 1000])
+def test_sphere_closed_form_and_fsum(D):
+    for c in (0.0, 1.0, -3.0, 7.0):
+        assert oracle.fitness("sphere", np.full(D, c)) == D * c * c
+    x = np.random.default_rng(D).uniform(-100, 100, D)
+    ref = math.fsum(float(v) * float(v) for v in x)
+    assert abs(oracle.fitness("sphere", x) - ref) <= 1e-15 * ref
+
+
+def test_rastrigin_optimum_integer_and_half_points():
+    D = 50
+    rng = np.random.default_rng(1)
+    o = rng.uniform(-4, 4, D)
+    assert oracle.fitness("rastrigin", o, o) == 0.0
+    z = rng.integers(-5, 6, D).astype(np.float64)
+    o2 = np.zeros(D)
+    f = oracle.fitness("rastrigin", z, o2)
+    assert abs(f - float((z * z).sum())) <= 1e-14 * max(1.0, f)
+    h = z + 0.5
+    f = oracle.fitness("rastrigin", h, o2)
+    ref = float((h * h).sum()) + 20.0 * D
+    assert abs(f - ref) <= 1e-14 * ref
+
+
+def test_rastrigin_matches_cosine_form():
+    # f = sum z^2 - 10 cos(2 pi z) + 10, evaluated with numpy's cos
+    D = 1000
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-5.12, 5.12, D)
+    o = rng.uniform(-4, 4, D)
+    z = x - o
+    ref = float(np.sum(z * z - 10.0 * np.cos(2.0 * np.pi * z) + 10.0))
+    f = oracle.fitness("rastrigin", x, o)
+    # the cosine form loses up to ~20 ulp of 10 per term to cancellation
+    assert abs(f - ref) <= 1e-13 * 20.0 * D
+
+
+@pytest.mark.parametrize("D", [2, 3, 10, 500])
+def test_rosenbrock_against_scipy_and_special_points(D):
+    rng = np.random.default_rng(D)
+    x = rng.uniform(-5.12, 5.12, D)
+    ones = np.ones(D)
+    # with o = 1 the shifted variable z = x - o + 1 is x itself
+    ref = float(rosen(x))
+    assert abs(oracle.fitness("rosenbrock", x, ones) - ref) <= 1e-13 * ref
+    o = rng.uniform(-4, 4, D)
+    assert oracle.fitness("rosenbrock", o, o) == 0.0                      # z = 1
+    assert oracle.fitness("rosenbrock", o - 1.0, o) == pytest.approx(D - 1, rel=1e-15)  # z = 0
+    assert oracle.fitness_phi("rosenbrock", x, o) >= oracle.fitness("rosenbrock", x, o)
+
+
+def test_ellipsoid_weights_and_special_points():
+    D = 16
+    w = oracle.ellipsoid_weights(D)
+    assert w[0] == 1.0 and w[-1] == 1e6
+    ratios = w[1:] / w[:-1]
+    assert np.allclose(ratios, 10 ** (6 / (D - 1)), rtol=1e-14)
+    eye = np.eye(D)
+    o = np.random.default_rng(3).uniform(-80, 80, D)
+    for k in range(D):
+        x = o + eye[k]
+        assert oracle.fitness("ellipsoid_rot", x, o, eye) == pytest.approx(w[k], rel=1e-15)
+    assert oracle.fitness("ellipsoid_rot", o, o, eye) == 0.0
+    perm = np.random.default_rng(4).permutation(D)
+    P = eye[perm]                        # (P d)_k = d_perm[k]
+    d = np.arange(1.0, D + 1.0)
+    f = oracle.fitness("ellipsoid_rot", o + d, o, P)
+    assert f == pytest.approx(float(np.sum(w * d[perm] ** 2)), rel=1e-15)
+
+
+def test_ellipsoid_rotated_against_numpy():
+    D = 64
+    rng = np.random.default_rng(0)
+    Q, R = np.linalg.qr(rng.standard_normal((D, D)))
+    Q = Q * np.sign(np.diag(R))
+    x = rng.uniform(-100, 100, D)
+    o = rng.uniform(-80, 80, D)
+    w = oracle.ellipsoid_weights(D)
+    ref = float(np.sum(w * (Q @ (x - o)) ** 2))
+    assert abs(oracle.fitness("ellipsoid_rot", x, o, Q) - ref) <= 1e-12 * ref
+
+
+def test_nan_is_plus_infinity():
+    x = np.array([1.0, np.nan, 2.0])
+    assert oracle.fitness("sphere", x) == math.inf
+    assert oracle.fitness("rastrigin", x, np.zeros(3)) == math.inf
+    assert oracle.fitness("rosenbrock", x, np.zeros(3)) == math.inf
