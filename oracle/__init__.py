@@ -39,7 +39,8 @@ class _Desc(C.Structure):
     _fields_ = [("N", C.c_int64), ("D", C.c_int64), ("F", C.c_double), ("CR", C.c_double),
                 ("xo", C.c_int32), ("fn", C.c_int32), ("dtype", C.c_int32), ("run", C.c_int32),
                 ("lo", C.c_double), ("hi", C.c_double), ("olo", C.c_double), ("ohi", C.c_double),
-                ("seed", C.c_uint64), ("shift", C.c_void_p), ("rot", C.c_void_p)]
+                ("seed", C.c_uint64), ("shift", C.c_void_p), ("rot", C.c_void_p),
+                ("lazy", C.c_int32), ("pad", C.c_int32)]
 
 
 def lib():
@@ -91,6 +92,8 @@ def lib():
                                        C.c_int64]
         L.oracle_get_best.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_get_shift.argtypes = [C.c_void_p, f64p]
+        L.oracle_individual.argtypes = [C.c_void_p, f64p, C.c_int64, C.c_int64, i64p, u8p, f64p,
+                                        C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -205,7 +208,7 @@ class Run:
     hold float32 values exactly)."""
 
     def __init__(self, N, D, F=0.5, CR=0.9, xo="bin", fn="sphere", dtype="fp64", lo=-100.0,
-                 hi=100.0, olo=0.0, ohi=0.0, seed=0, run=0, shift=None, rot=None):
+                 hi=100.0, olo=0.0, ohi=0.0, seed=0, run=0, shift=None, rot=None, lazy=False):
         self.N, self.D = int(N), int(D)
         self.dtype = dtype
         self.fn = fn
@@ -216,7 +219,7 @@ class Run:
         d = _Desc(N=self.N, D=self.D, F=F, CR=CR, xo=XO[xo], fn=FN[fn], dtype=DTYPE[dtype], run=run,
                   lo=lo, hi=hi, olo=olo, ohi=ohi, seed=seed,
                   shift=None if sh is None else sh.ctypes.data,
-                  rot=None if rt is None else rt.ctypes.data)
+                  rot=None if rt is None else rt.ctypes.data, lazy=1 if lazy else 0)
         self._h = lib().oracle_create(C.byref(d))
         if not self._h:
             raise ValueError("oracle_create rejected the run description")
@@ -259,6 +262,16 @@ class Run:
         x = np.zeros(self.D, np.float64)
         lib().oracle_get_best(self._h, C.byref(f), C.byref(idx), C.byref(g), _ptr(x))
         return f.value, idx.value, g.value, x
+
+    def individual(self, pop, g, i):
+        """Generation g's trial of individual i from population pop (N x D)."""
+        idx = np.zeros(6, np.int64)
+        m = np.zeros(self.D, np.uint8)
+        u = np.zeros(self.D, np.float64)
+        f = C.c_double(0)
+        lib().oracle_individual(self._h, np.ascontiguousarray(pop, np.float64), int(g), int(i), idx,
+                                m, u, C.byref(f))
+        return {"idx": idx, "mask": m, "trial": u, "ftrial": f.value}
 
     def shift(self):
         o = np.zeros(self.D, np.float64)

@@ -319,7 +319,7 @@ oracle_state* oracle_create(const oracle_desc* d) {
   for (int64_t i = 0; i < N; ++i)
     for (int64_t j = 0; j < D; ++j)
       s->x[i * D + j] = init_value(d, OR_TAG_INIT, (uint32_t)i, j, d->lo, d->hi);
-  for (int64_t i = 0; i < N; ++i) s->fit[i] = eval_row(s, s->x + i * D);
+  for (int64_t i = 0; i < N; ++i) s->fit[i] = d->lazy ? NAN : eval_row(s, s->x + i * D);
   s->gen = 0;
   s->best_f = INFINITY;
   s->best_idx = 0;
@@ -340,46 +340,56 @@ void oracle_destroy(oracle_state* s) {
  * x into u and overwrite the masked elements with the DE/rand/1 mutant
  * x_r0 + F (x_r1 - x_r2) (lines 8-9, Eq 1), evaluate u (line 10), then keep
  * u_i wherever f(u_i) < f_i strictly (lines 11-14, Alg 1 line 10). */
+/* Generation g's trial for individual i from population x (Alg 2 lines 6-10
+ * for one row): choose r0, r1, r2, build the crossover mask first (line 7),
+ * copy x_i and overwrite the masked elements with the DE/rand/1 mutant
+ * x_r0 + F (x_r1 - x_r2) (lines 8-9, Eq 1), then evaluate (line 10). */
+static void build_trial(const oracle_state* s, const double* x, uint32_t g, int64_t i,
+                        int64_t* t, uint8_t* m, double* ui, double* fu) {
+  const oracle_desc* d = &s->d;
+  int64_t N = d->N, D = d->D;
+  int64_t r[3];
+  oracle_indices(d->seed, (uint32_t)d->run, N, g, i, r);
+  uint32_t xw0 = oracle_word(d->seed, (uint32_t)d->run, OR_TAG_XO, g, (uint32_t)i, 0, 0);
+  uint32_t xw1 = oracle_word(d->seed, (uint32_t)d->run, OR_TAG_XO, g, (uint32_t)i, 0, 1);
+  int64_t jrand = oracle_randint(xw0, D);
+  int64_t L;
+  if (d->xo == OR_XO_BIN) {
+    oracle_mask_bin(d->seed, (uint32_t)d->run, D, d->CR, g, i, jrand, m);
+    L = 0;
+    for (int64_t j = 0; j < D; ++j) L += m[j];
+  } else {
+    if (d->xo == OR_XO_EXP) L = oracle_exp_length(d->seed, (uint32_t)d->run, D, d->CR, g, i);
+    else L = oracle_nec_length(oracle_uniform(xw1), d->CR, D);
+    oracle_alg9_mask(D, jrand, L, m);
+  }
+  const double* x0 = x + r[0] * D;
+  const double* x1 = x + r[1] * D;
+  const double* x2 = x + r[2] * D;
+  const double* xi = x + i * D;
+  for (int64_t j = 0; j < D; ++j) {
+    if (!m[j]) {
+      ui[j] = xi[j];
+    } else if (d->dtype == OR_FP64) {
+      ui[j] = fma(d->F, x1[j] - x2[j], x0[j]);
+    } else {
+      float diff = (float)x1[j] - (float)x2[j];
+      ui[j] = (double)fmaf((float)d->F, diff, (float)x0[j]);
+    }
+  }
+  *fu = eval_row(s, ui);
+  t[0] = r[0]; t[1] = r[1]; t[2] = r[2]; t[3] = jrand; t[4] = L; t[5] = 0;
+}
+
+/* One generation, Alg 2 lines 5-14 (without the shuffle of line 5): every
+ * trial is built from generation g-1, then u_i replaces x_i wherever
+ * f(u_i) < f_i strictly (lines 11-14, Alg 1 line 10). */
 static void one_generation(oracle_state* s) {
   const oracle_desc* d = &s->d;
   int64_t N = d->N, D = d->D;
   uint32_t g = (uint32_t)(s->gen + 1);
-  for (int64_t i = 0; i < N; ++i) {
-    int64_t r[3];
-    oracle_indices(d->seed, (uint32_t)d->run, N, g, i, r);
-    uint32_t xw0 = oracle_word(d->seed, (uint32_t)d->run, OR_TAG_XO, g, (uint32_t)i, 0, 0);
-    uint32_t xw1 = oracle_word(d->seed, (uint32_t)d->run, OR_TAG_XO, g, (uint32_t)i, 0, 1);
-    int64_t jrand = oracle_randint(xw0, D);
-    uint8_t* m = s->mask + i * D;
-    int64_t L;
-    if (d->xo == OR_XO_BIN) {
-      oracle_mask_bin(d->seed, (uint32_t)d->run, D, d->CR, g, i, jrand, m);
-      L = 0;
-      for (int64_t j = 0; j < D; ++j) L += m[j];
-    } else {
-      if (d->xo == OR_XO_EXP) L = oracle_exp_length(d->seed, (uint32_t)d->run, D, d->CR, g, i);
-      else L = oracle_nec_length(oracle_uniform(xw1), d->CR, D);
-      oracle_alg9_mask(D, jrand, L, m);
-    }
-    const double* x0 = s->x + r[0] * D;
-    const double* x1 = s->x + r[1] * D;
-    const double* x2 = s->x + r[2] * D;
-    const double* xi = s->x + i * D;
-    double* ui = s->u + i * D;
-    for (int64_t j = 0; j < D; ++j) {
-      if (!m[j]) {
-        ui[j] = xi[j];
-      } else if (d->dtype == OR_FP64) {
-        ui[j] = fma(d->F, x1[j] - x2[j], x0[j]);
-      } else {
-        float diff = (float)x1[j] - (float)x2[j];
-        ui[j] = (double)fmaf((float)d->F, diff, (float)x0[j]);
-      }
-    }
-    s->fu[i] = eval_row(s, ui);
-    int64_t* t = s->tr + 6 * i;
-    t[0] = r[0]; t[1] = r[1]; t[2] = r[2]; t[3] = jrand; t[4] = L; t[5] = 0;
-  }
+  for (int64_t i = 0; i < N; ++i)
+    build_trial(s, s->x, g, i, s->tr + 6 * i, s->mask + i * D, s->u + i * D, s->fu + i);
   s->gen += 1;
   for (int64_t i = 0; i < N; ++i) {
     if (s->fu[i] < s->fit[i]) {
@@ -391,9 +401,14 @@ static void one_generation(oracle_state* s) {
   update_best(s);
 }
 
+void oracle_individual(const oracle_state* s, const double* pop, int64_t g, int64_t i,
+                       int64_t* idx6, uint8_t* mask, double* trial, double* ftrial) {
+  build_trial(s, pop, (uint32_t)g, i, idx6, mask, trial, ftrial);
+}
+
 int oracle_generation(oracle_state* s, int64_t n, int64_t* trace_idx, uint8_t* trace_mask,
                       double* trace_trial, double* trace_ftrial) {
-  if (!s || n < 0) return 1;
+  if (!s || n < 0 || s->d.lazy) return 1;
   for (int64_t k = 0; k < n; ++k) one_generation(s);
   if (n > 0) {
     int64_t N = s->d.N, D = s->d.D;

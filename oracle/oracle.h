@@ -81,6 +81,8 @@ typedef struct {
   uint64_t seed;
   const double* shift;  /* D values or NULL */
   const double* rot;    /* D x D row-major, rotated ellipsoid only */
+  int32_t lazy;         /* 1: skip the initial evaluation (per-individual use only) */
+  int32_t pad;
 } oracle_desc;
 
 typedef struct oracle_state oracle_state;
@@ -97,6 +99,11 @@ void oracle_set_state(oracle_state* s, const double* pop, const double* fit, int
                       double best_f, int64_t best_idx, int64_t best_gen);
 void oracle_get_best(const oracle_state* s, double* f, int64_t* idx, int64_t* gen, double* xbest);
 void oracle_get_shift(const oracle_state* s, double* o);
+/* Generation g's trial of individual i built from the population `pop`
+ * (N x D, the population after generation g-1): idx6 = r0, r1, r2, jrand, L,
+ * 0; mask and trial D values; *ftrial = f(trial). */
+void oracle_individual(const oracle_state* s, const double* pop, int64_t g, int64_t i,
+                       int64_t* idx6, uint8_t* mask, double* trial, double* ftrial);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,171 @@
+// Device-side building blocks: the counter-based generator, the integer maps
+// that turn its words into indices, lengths and masks, and the fitness terms.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "de_internal.h"
+
+namespace de {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten S-box rounds on a
+// 128-bit counter; each round multiplies words 0 and 2 by the two Philox
+// constants, and the two-word key advances by the Weyl constants between
+// rounds.  The 64-bit products give high and low halves in one multiply.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t q = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t n0 = static_cast<uint32_t>(q >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(p >> 32) ^ c3 ^ k1;
+    c1 = static_cast<uint32_t>(q);
+    c3 = static_cast<uint32_t>(p);
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// Block `blk` of stream `tag` for individual i in generation g of run `run`.
+__device__ __forceinline__ uint4 draw(const RunDev& P, uint32_t tag, uint32_t g, uint32_t i,
+                                      uint32_t blk) {
+  return philox(blk, i, g, (tag << 24) | (P.run_id & 0xFFFFFFu), P.key0, P.key1);
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4& b, int k) {
+  return k == 0 ? b.x : k == 1 ? b.y : k == 2 ? b.z : b.w;
+}
+
+// floor(n * w / 2^32): an index in [0, n).
+__device__ __forceinline__ uint32_t scale_index(uint32_t w, uint32_t n) {
+  return static_cast<uint32_t>((static_cast<uint64_t>(w) * n) >> 32);
+}
+
+// Base r0 and difference pair r1, r2 of DE/rand/1, all distinct and != i:
+// draw from the shrunken range, then step over the excluded rows in
+// increasing order.
+__device__ __forceinline__ void pick_indices(uint4 b, uint32_t N, uint32_t i, uint32_t& r0,
+                                             uint32_t& r1, uint32_t& r2) {
+  r0 = scale_index(b.x, N - 1);
+  r0 += (r0 >= i);
+  const uint32_t a = min(i, r0), c = max(i, r0);
+  r1 = scale_index(b.y, N - 2);
+  r1 += (r1 >= a);
+  r1 += (r1 >= c);
+  uint32_t e0 = a, e1 = c, e2 = r1;  // sort three excluded rows
+  if (e2 < e1) { uint32_t t = e1; e1 = e2; e2 = t; }
+  if (e1 < e0) { uint32_t t = e0; e0 = e1; e1 = t; }
+  r2 = scale_index(b.z, N - 3);
+  r2 += (r2 >= e0);
+  r2 += (r2 >= e1);
+  r2 += (r2 >= e2);
+}
+
+// NEC run length from word w: the number of k in [1, D] with w < T[k], where
+// T[k] counts the words whose uniform lies below CR^(k-1).  A logarithm gives
+// the starting guess; the table settles it exactly.
+__device__ __forceinline__ uint32_t nec_length(const RunDev& P, uint32_t w) {
+  const uint32_t D = static_cast<uint32_t>(P.D);
+  if (P.inv_ln_cr == 0.0) return P.CR >= 1.0 ? D : 1u;
+  const float U = (static_cast<float>(w) + 0.5f) * 0x1p-32f;
+  float e = ceilf(__logf(U) * static_cast<float>(P.inv_ln_cr));
+  uint32_t L = e < 1.0f ? 1u : (e >= static_cast<float>(D) ? D : static_cast<uint32_t>(e));
+  const uint64_t ww = w;
+  while (L > 1 && !(ww < P.T[L])) --L;
+  while (L < D && ww < P.T[L + 1]) ++L;
+  return L;
+}
+
+// Classic exponential crossover length (Alg 8), draws taken one at a time in
+// order: draw e (EXP block e/4, word e%4) decides whether element e+2 joins.
+__device__ __forceinline__ uint32_t exp_length_serial(const RunDev& P, uint32_t g, uint32_t i) {
+  const uint32_t D = static_cast<uint32_t>(P.D);
+  uint32_t L = 1;
+  uint4 b = make_uint4(0, 0, 0, 0);
+  for (uint32_t e = 0; L < D; ++e) {
+    if ((e & 3u) == 0) b = draw(P, TAG_EXP, g, i, e >> 2);
+    if (static_cast<uint64_t>(word_of(b, e & 3u)) < P.thr) ++L;
+    else break;
+  }
+  return L;
+}
+
+// The same length found 256 draws at a time by one wavefront: each lane tests
+// one Philox block (4 draws) and the lowest failing draw ends the run.
+__device__ __forceinline__ uint32_t exp_length_scan(const RunDev& P, uint32_t g, uint32_t i) {
+  const uint32_t D = static_cast<uint32_t>(P.D);
+  const uint32_t lane = __lane_id();
+  for (uint32_t base = 0; base + 1 < D; base += 256) {
+    const uint32_t e0 = base + 4 * lane;
+    const uint4 b = draw(P, TAG_EXP, g, i, e0 >> 2);
+    uint32_t fail = 4;
+#pragma unroll
+    for (int k = 3; k >= 0; --k)
+      if (static_cast<uint64_t>(word_of(b, k)) >= P.thr) fail = k;
+    const bool hit = fail < 4 && e0 + fail + 1 < D;
+    const uint64_t bal = __ballot(hit);
+    if (bal) {
+      const uint32_t first = __ffsll(static_cast<unsigned long long>(bal)) - 1;
+      const uint32_t f = __shfl(fail, first);
+      return base + 4 * first + f + 1;  // draws 0..e-1 passed, draw e failed: L = e + 1
+    }
+  }
+  return D;
+}
+
+// ---- fitness terms --------------------------------------------------------
+template <typename T> struct Math;
+template <> struct Math<double> {
+  static __device__ __forceinline__ double fma_(double a, double b, double c) {
+    return __builtin_fma(a, b, c);
+  }
+  static __device__ __forceinline__ double sinpi_(double x) { return sinpi(x); }
+  static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
+};
+template <> struct Math<float> {
+  static __device__ __forceinline__ float fma_(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+  }
+  static __device__ __forceinline__ float sinpi_(float x) { return sinpif(x); }
+  static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
+};
+
+// Separable per-element term: sphere x^2, Rastrigin z^2 + 20 sin^2(pi z)
+// (= z^2 - 10 cos(2 pi z) + 10 without the cancellation near integers).
+template <typename T, int FN>
+__device__ __forceinline__ T point_term(T x, T o) {
+  if constexpr (FN == FN_SPHERE) {
+    return x * x;
+  } else {
+    const T z = x - o;
+    const T s = Math<T>::sinpi_(z);
+    return Math<T>::fma_(z, z, T(20) * (s * s));
+  }
+}
+
+// Rosenbrock pair term for z_j, z_{j+1} with z = x - o + 1.
+template <typename T>
+__device__ __forceinline__ T rosen_term(T z0, T z1) {
+  const T a = z1 - z0 * z0;
+  const T b = z0 - T(1);
+  return Math<T>::fma_(T(100) * a, a, b * b);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T canon(T f) {
+  return f != f ? Math<T>::inf() : f;
+}
+
+}  // namespace de

@@ -1,0 +1,557 @@
+// C ABI of the library (declared in include/de.h): argument checks, the
+// workspace layout, launch sequencing per generation and state transfer.
+// No device memory is allocated here: every device byte comes from the
+// caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "de.h"
+#include "de_internal.h"
+
+using de::RunDev;
+using de::BestState;
+
+struct de_handle {
+  int n_runs = 0;
+  bool batched = false;
+  int dtype = 0;
+  std::vector<de_run_desc> desc;
+  std::vector<RunDev> host;          // mirror of the device records
+  RunDev* dev_runs = nullptr;
+  BestState* best = nullptr;
+  double* scratch_f64 = nullptr;     // one FP64 for de_best
+  uint2* rowmap = nullptr;
+  int64_t total_rows = 0;
+  std::vector<uint2> rowmap_host;
+  std::vector<std::vector<uint64_t>> tables;  // host copies of the NEC tables
+  std::vector<int> tpr;
+  std::string err;
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+de_status fail(de_handle* h, de_status st, const std::string& msg) {
+  if (h) h->err = msg;
+  g_err = msg;
+  return st;
+}
+
+de_status hip_fail(de_handle* h, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(h, DE_E_HIP, m);
+}
+
+#define HIPCHECK(h, expr)                                   \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #expr);  \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int64_t up64(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int esz(int dtype) { return dtype == DE_FP64 ? 8 : 4; }
+int mm_pieces(int mm) { return mm == DE_MM_BF16X6 ? 3 : (mm == DE_MM_BF16X3 ? 2 : 1); }
+int mm_elem(int mm) { return mm == DE_MM_FP64 ? 8 : (mm == DE_MM_FP32 ? 4 : 2); }
+int mm_tile_n(int mm) { return mm == DE_MM_FP64 ? 64 : 128; }
+
+// Number of words w with (w + 1/2) 2^-32 < p, i.e. ceil(p 2^32 - 1/2) clamped
+// to [0, 2^32]; exact in FP64 for p in [0, 1].
+uint64_t threshold(double p) {
+  double v = std::ceil(std::ldexp(p, 32) - 0.5);
+  if (!(v > 0.0)) return 0;
+  if (v >= 4294967296.0) return 4294967296ull;
+  return static_cast<uint64_t>(v);
+}
+
+struct Layout {
+  size_t total = 0;
+  size_t runs_off = 0, best_off = 0, scratch_off = 0, rowmap_off = 0;
+  struct Run {
+    size_t X0, X1, fit, flags, o, T, w, B[3], part, stage;
+    int64_t ld, ldk, ntile;
+  };
+  std::vector<Run> r;
+};
+
+size_t bump(size_t& cur, size_t bytes) {
+  size_t at = cur;
+  cur = up(cur + bytes, kAlign);
+  return at;
+}
+
+de_status validate(const de_run_desc* runs, int32_t n_runs, std::string& msg) {
+  if (!runs || n_runs < 1) { msg = "runs must be a non-empty array"; return DE_E_INVALID; }
+  for (int r = 0; r < n_runs; ++r) {
+    const de_run_desc& d = runs[r];
+    char buf[160];
+    auto bad = [&](const char* what) {
+      std::snprintf(buf, sizeof buf, "run %d: %s", r, what);
+      msg = buf;
+      return DE_E_INVALID;
+    };
+    if (d.N < 4 || d.N >= (1 << 21)) return bad("N must satisfy 4 <= N < 2^21");
+    if (d.D < 1 || d.D >= (1 << 21)) return bad("D must satisfy 1 <= D < 2^21");
+    if (!(d.CR >= 0.0 && d.CR <= 1.0)) return bad("CR must lie in [0, 1]");
+    if (!std::isfinite(d.F) || d.F < 0.0) return bad("F must be finite and >= 0");
+    if (!(std::isfinite(d.lo) && std::isfinite(d.hi) && d.lo < d.hi)) return bad("need finite lo < hi");
+    if (d.dtype != DE_FP64 && d.dtype != DE_FP32) return bad("unknown dtype");
+    if (d.xo < DE_XO_BIN || d.xo > DE_XO_NEC) return bad("unknown crossover");
+    if (d.fn < DE_FN_SPHERE || d.fn > DE_FN_ELLIPSOID_ROT) return bad("unknown function");
+    if (d.exp_impl < DE_EXP_LANE || d.exp_impl > DE_EXP_SCAN) return bad("unknown exp_impl");
+    if (d.reserved != 0) return bad("reserved must be 0");
+    if (d.fn != DE_FN_SPHERE && !d.shift &&
+        !(std::isfinite(d.olo) && std::isfinite(d.ohi) && d.olo <= d.ohi))
+      return bad("need finite olo <= ohi when shift is NULL");
+    if (d.fn == DE_FN_ELLIPSOID_ROT) {
+      if (d.D < 2) return bad("the rotated function needs D >= 2");
+      if (!d.rot) return bad("the rotated function needs rot");
+      if (d.mm < DE_MM_FP64 || d.mm > DE_MM_BF16X6) return bad("unknown matmul mode");
+      const bool ok = (d.dtype == DE_FP64 && d.mm == DE_MM_FP64) ||
+                      (d.dtype == DE_FP32 && d.mm != DE_MM_FP64);
+      if (!ok) {
+        std::snprintf(buf, sizeof buf, "run %d: matmul mode %d does not go with dtype %d", r,
+                      d.mm, d.dtype);
+        msg = buf;
+        return DE_E_UNSUPPORTED;
+      }
+    }
+    if (n_runs > 1) {
+      if (d.fn == DE_FN_ELLIPSOID_ROT || (d.xo == DE_XO_EXP && d.exp_impl == DE_EXP_JOB)) {
+        std::snprintf(buf, sizeof buf,
+                      "run %d: batched launches support the separable functions and the "
+                      "lane/scan exponential crossover only", r);
+        msg = buf;
+        return DE_E_UNSUPPORTED;
+      }
+      if (d.dtype != runs[0].dtype) {
+        msg = "all runs of a batch must share one dtype";
+        return DE_E_UNSUPPORTED;
+      }
+    }
+  }
+  return DE_OK;
+}
+
+Layout layout(const de_run_desc* runs, int32_t n_runs) {
+  Layout L;
+  size_t cur = 0;
+  L.runs_off = bump(cur, sizeof(RunDev) * n_runs);
+  L.best_off = bump(cur, sizeof(BestState) * n_runs);
+  L.scratch_off = bump(cur, 64);
+  int64_t total_rows = 0;
+  for (int r = 0; r < n_runs; ++r) total_rows += runs[r].N;
+  L.rowmap_off = bump(cur, n_runs > 1 ? sizeof(uint2) * total_rows : 0);
+  L.r.resize(n_runs);
+  for (int r = 0; r < n_runs; ++r) {
+    const de_run_desc& d = runs[r];
+    Layout::Run& q = L.r[r];
+    const size_t s = esz(d.dtype);
+    q.ld = up64(d.D, 32);
+    const size_t pop = s * d.N * q.ld;
+    q.X0 = bump(cur, pop);
+    q.X1 = bump(cur, pop);
+    q.fit = bump(cur, s * d.N);
+    q.flags = bump(cur, 2 * d.N);
+    q.o = bump(cur, s * q.ld);
+    q.T = bump(cur, 8 * (d.D + 2));
+    q.ldk = 0;
+    q.ntile = 0;
+    q.w = q.part = q.stage = 0;
+    q.B[0] = q.B[1] = q.B[2] = 0;
+    if (d.fn == DE_FN_ELLIPSOID_ROT) {
+      q.ldk = up64(d.D, 32);
+      q.ntile = (d.D + mm_tile_n(d.mm) - 1) / mm_tile_n(d.mm);
+      const int64_t rows_pad = up64(d.D, 128);
+      q.w = bump(cur, s * d.D);
+      for (int p = 0; p < mm_pieces(d.mm); ++p)
+        q.B[p] = bump(cur, static_cast<size_t>(mm_elem(d.mm)) * rows_pad * q.ldk);
+      q.part = bump(cur, s * d.N * q.ntile);
+      q.stage = bump(cur, pop);
+    }
+  }
+  L.total = cur;
+  return L;
+}
+
+int pick_tpr(const de_run_desc& d, bool batched) {
+  if (batched) return 64;
+  if (const char* e = std::getenv("DE_TPR")) {
+    int v = std::atoi(e);
+    if (v == 64 || v == 256 || v == 1024) return v;
+  }
+  const int64_t nchunk = (d.D + 3) / 4;
+  if (nchunk <= 64 * 4) return 64;
+  if (nchunk <= 256 * 4) return 256;
+  return 1024;
+}
+
+hipError_t upload_run(de_handle* h, int r, hipStream_t s) {
+  return hipMemcpyAsync(h->dev_runs + r, &h->host[r], sizeof(RunDev), hipMemcpyHostToDevice, s);
+}
+
+hipEvent_t next_event(de_handle* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// The launches of one generation of one run (single-run handles) or of all
+// runs (batched); `main` brackets the dominant kernel with events if enabled.
+de_status one_generation(de_handle* h, hipStream_t s) {
+  auto mark = [&](bool on) -> hipEvent_t {
+    if (!h->prof || !on) return nullptr;
+    hipEvent_t e = next_event(h);
+    if (e) (void)hipEventRecord(e, s);
+    return e;
+  };
+  if (h->batched) {
+    de::GenLaunch L{h->dev_runs, h->host.data(), 0, h->rowmap, h->total_rows, 64, s};
+    mark(true);
+    HIPCHECK(h, de::launch_generation(L, de::FN_ANY, de::XO_ANY, h->dtype, true));
+    mark(true);
+  } else {
+    for (int r = 0; r < h->n_runs; ++r) {
+      const de_run_desc& d = h->desc[r];
+      const RunDev& H = h->host[r];
+      const bool job = d.xo == DE_XO_EXP && d.exp_impl == DE_EXP_JOB;
+      if (d.fn == DE_FN_ELLIPSOID_ROT) {
+        if (job) {
+          HIPCHECK(h, de::launch_pexp_trial(h->dev_runs, H, r, s));
+        } else {
+          de::GenLaunch L{h->dev_runs, h->host.data(), r, nullptr, d.N, h->tpr[r], s};
+          HIPCHECK(h, de::launch_generation(L, de::FN_NONE, d.xo, d.dtype, false));
+        }
+        mark(true);
+        HIPCHECK(h, de::launch_rot_fitness(h->dev_runs, H, r, true, s));
+        mark(true);
+        HIPCHECK(h, de::launch_rot_select(h->dev_runs, H, r, s));
+      } else if (job) {
+        mark(true);
+        HIPCHECK(h, de::launch_pexp_trial(h->dev_runs, H, r, s));
+        mark(true);
+        HIPCHECK(h, de::launch_eval_select(h->dev_runs, H, r, s));
+      } else {
+        de::GenLaunch L{h->dev_runs, h->host.data(), r, nullptr, d.N, h->tpr[r], s};
+        mark(true);
+        HIPCHECK(h, de::launch_generation(L, d.fn, d.xo, d.dtype, false));
+        mark(true);
+      }
+    }
+  }
+  HIPCHECK(h, de::launch_best(h->dev_runs, h->n_runs, false, s));
+  return DE_OK;
+}
+
+de_status check_run(de_handle* h, int32_t run) {
+  if (!h) return fail(nullptr, DE_E_INVALID, "NULL handle");
+  if (run < 0 || run >= h->n_runs) return fail(h, DE_E_INVALID, "run index out of range");
+  return DE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+de_status de_workspace_size(const de_run_desc* runs, int32_t n_runs, size_t* bytes) {
+  std::string msg;
+  de_status st = validate(runs, n_runs, msg);
+  if (st != DE_OK) return fail(nullptr, st, msg);
+  if (!bytes) return fail(nullptr, DE_E_INVALID, "bytes is NULL");
+  *bytes = layout(runs, n_runs).total;
+  return DE_OK;
+}
+
+de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void* workspace,
+                  size_t ws_bytes, void* stream) {
+  if (!out) return fail(nullptr, DE_E_INVALID, "h is NULL");
+  *out = nullptr;
+  std::string msg;
+  de_status st = validate(runs, n_runs, msg);
+  if (st != DE_OK) return fail(nullptr, st, msg);
+  const Layout L = layout(runs, n_runs);
+  if (!workspace) return fail(nullptr, DE_E_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(nullptr, DE_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(nullptr, DE_E_WORKSPACE, "workspace too small");
+
+  de_handle* h = new de_handle();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  h->n_runs = n_runs;
+  h->batched = n_runs > 1;
+  h->dtype = runs[0].dtype;
+  h->desc.assign(runs, runs + n_runs);
+  h->dev_runs = reinterpret_cast<RunDev*>(ws + L.runs_off);
+  h->best = reinterpret_cast<BestState*>(ws + L.best_off);
+  h->scratch_f64 = reinterpret_cast<double*>(ws + L.scratch_off);
+  h->rowmap = h->batched ? reinterpret_cast<uint2*>(ws + L.rowmap_off) : nullptr;
+  h->host.resize(n_runs);
+  h->tables.resize(n_runs);
+  h->tpr.resize(n_runs);
+  for (int r = 0; r < n_runs; ++r) {
+    const de_run_desc& d = runs[r];
+    const Layout::Run& q = L.r[r];
+    RunDev& R = h->host[r];
+    std::memset(&R, 0, sizeof R);
+    R.N = d.N; R.D = d.D; R.ld = q.ld;
+    R.F = d.F; R.CR = d.CR; R.Ff = static_cast<float>(d.F);
+    R.inv_ln_cr = (d.CR > 0.0 && d.CR < 1.0) ? 1.0 / std::log(d.CR) : 0.0;
+    R.thr = threshold(d.CR);
+    R.key0 = static_cast<uint32_t>(d.seed);
+    R.key1 = static_cast<uint32_t>(d.seed >> 32);
+    R.run_id = static_cast<uint32_t>(r);
+    R.fn = d.fn; R.xo = d.xo; R.exp_impl = d.exp_impl; R.dtype = d.dtype; R.mm = d.mm;
+    R.X[0] = ws + q.X0;
+    R.X[1] = ws + q.X1;
+    R.fit = ws + q.fit;
+    R.flags = reinterpret_cast<uint8_t*>(ws + q.flags);
+    R.o = ws + q.o;
+    R.T = reinterpret_cast<const uint64_t*>(ws + q.T);
+    R.best = h->best + r;
+    if (d.fn == DE_FN_ELLIPSOID_ROT) {
+      R.rot = d.rot;
+      R.w = ws + q.w;
+      for (int p = 0; p < mm_pieces(d.mm); ++p) R.B[p] = ws + q.B[p];
+      R.ldk = q.ldk;
+      R.part = ws + q.part;
+      R.ntile = static_cast<int32_t>(q.ntile);
+      R.stage = ws + q.stage;
+    }
+    // NEC thresholds: T[k] = #words below CR^(k-1), the power taken as a
+    // running FP64 product; T[D+1] = 0 ends the search.
+    std::vector<uint64_t>& T = h->tables[r];
+    T.assign(d.D + 2, 0);
+    T[0] = 4294967296ull;
+    double t = 1.0;
+    for (int64_t k = 1; k <= d.D; ++k) {
+      if (k > 1) t = t * d.CR;
+      T[k] = threshold(t);
+    }
+    T[d.D + 1] = 0;
+    h->tpr[r] = pick_tpr(d, h->batched);
+  }
+  if (h->batched) {
+    for (int r = 0; r < n_runs; ++r)
+      for (int64_t i = 0; i < runs[r].N; ++i)
+        h->rowmap_host.push_back(make_uint2(static_cast<unsigned>(r), static_cast<unsigned>(i)));
+    h->total_rows = static_cast<int64_t>(h->rowmap_host.size());
+  }
+
+  auto bail = [&](de_status st2) {
+    g_err = h->err;
+    delete h;
+    return st2;
+  };
+#define HIPINIT(expr)                                          \
+  do {                                                         \
+    hipError_t e_ = (expr);                                    \
+    if (e_ != hipSuccess) return bail(hip_fail(h, e_, #expr)); \
+  } while (0)
+
+  HIPINIT(hipMemcpyAsync(h->dev_runs, h->host.data(), sizeof(RunDev) * n_runs,
+                         hipMemcpyHostToDevice, s));
+  if (h->batched)
+    HIPINIT(hipMemcpyAsync(h->rowmap, h->rowmap_host.data(), sizeof(uint2) * h->total_rows,
+                           hipMemcpyHostToDevice, s));
+  for (int r = 0; r < n_runs; ++r) {
+    const de_run_desc& d = runs[r];
+    const RunDev& R = h->host[r];
+    HIPINIT(hipMemcpyAsync(const_cast<uint64_t*>(R.T), h->tables[r].data(),
+                           sizeof(uint64_t) * (d.D + 2), hipMemcpyHostToDevice, s));
+    HIPINIT(de::launch_init_impl(h->dev_runs, R, r, d.lo, d.hi, d.olo, d.ohi,
+                                 d.fn == DE_FN_SPHERE ? nullptr : d.shift, s));
+    if (d.fn == DE_FN_ELLIPSOID_ROT) {
+      HIPINIT(de::launch_prepare_rot(R, s));
+      HIPINIT(de::launch_rot_init_fit(h->dev_runs, R, r, s));
+    } else {
+      HIPINIT(de::launch_eval_pop(h->dev_runs, R, r, s));
+    }
+  }
+  HIPINIT(de::launch_best(h->dev_runs, n_runs, true, s));
+  // host tables must outlive the asynchronous copies
+  HIPINIT(hipStreamSynchronize(s));
+#undef HIPINIT
+  *out = h;
+  return DE_OK;
+}
+
+de_status de_generation(de_handle* h, int32_t n_gens, void* stream) {
+  if (!h) return fail(nullptr, DE_E_INVALID, "NULL handle");
+  if (n_gens < 0) return fail(h, DE_E_INVALID, "n_gens must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int32_t k = 0; k < n_gens; ++k) {
+    de_status st = one_generation(h, s);
+    if (st != DE_OK) return st;
+  }
+  return DE_OK;
+}
+
+de_status de_evaluate(de_handle* h, int32_t run, const void* X, int64_t rows, void* fit_out,
+                      void* stream) {
+  de_status st = check_run(h, run);
+  if (st != DE_OK) return st;
+  if (rows < 0) return fail(h, DE_E_INVALID, "rows must be >= 0");
+  if (rows > 0 && (!X || !fit_out)) return fail(h, DE_E_INVALID, "X and fit_out are required");
+  if (rows == 0) return DE_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const RunDev& R = h->host[run];
+  if (R.fn == DE_FN_ELLIPSOID_ROT) {
+    HIPCHECK(h, de::launch_rot_eval_rows(h->dev_runs, R, run, X, rows, fit_out, s));
+  } else {
+    HIPCHECK(h, de::launch_eval_rows(R, X, rows, R.D, fit_out, s));
+  }
+  return DE_OK;
+}
+
+de_status de_best(de_handle* h, int32_t run, double* f_best, int64_t* idx, int64_t* gen,
+                  void* x_best_host, void* stream) {
+  de_status st = check_run(h, run);
+  if (st != DE_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const RunDev& R = h->host[run];
+  HIPCHECK(h, de::launch_best_fp64(h->dev_runs, R, run, h->scratch_f64, s));
+  BestState B;
+  double f = 0.0;
+  HIPCHECK(h, hipMemcpyAsync(&B, h->best + run, sizeof B, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipMemcpyAsync(&f, h->scratch_f64, sizeof f, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipStreamSynchronize(s));
+  if (f_best) *f_best = f;
+  if (idx) *idx = B.idx;
+  if (gen) *gen = B.gen;
+  if (x_best_host) {
+    uint8_t flag = 0;
+    HIPCHECK(h, hipMemcpyAsync(&flag, R.flags + (B.g & 1u) * R.N + B.idx, 1,
+                               hipMemcpyDeviceToHost, s));
+    HIPCHECK(h, hipStreamSynchronize(s));
+    const size_t e = esz(R.dtype);
+    const char* src = static_cast<const char*>(R.X[flag ? 1 : 0]) + e * B.idx * R.ld;
+    HIPCHECK(h, hipMemcpyAsync(x_best_host, src, e * R.D, hipMemcpyDeviceToHost, s));
+    HIPCHECK(h, hipStreamSynchronize(s));
+  }
+  return DE_OK;
+}
+
+de_status de_get_state(de_handle* h, int32_t run, void* pop_host, void* fit_host, int64_t* gen,
+                       void* stream) {
+  de_status st = check_run(h, run);
+  if (st != DE_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const RunDev& R = h->host[run];
+  const size_t e = esz(R.dtype);
+  if (pop_host) {
+    HIPCHECK(h, de::launch_normalize(h->dev_runs, R, run, s));
+    HIPCHECK(h, hipMemcpy2DAsync(pop_host, e * R.D, R.X[0], e * R.ld, e * R.D, R.N,
+                                 hipMemcpyDeviceToHost, s));
+  }
+  if (fit_host) HIPCHECK(h, hipMemcpyAsync(fit_host, R.fit, e * R.N, hipMemcpyDeviceToHost, s));
+  BestState B;
+  HIPCHECK(h, hipMemcpyAsync(&B, h->best + run, sizeof B, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipStreamSynchronize(s));
+  if (gen) *gen = B.g;
+  return DE_OK;
+}
+
+de_status de_set_state(de_handle* h, int32_t run, const void* pop_host, const void* fit_host,
+                       int64_t gen, double best_f, int64_t best_idx, int64_t best_gen,
+                       void* stream) {
+  de_status st = check_run(h, run);
+  if (st != DE_OK) return st;
+  if (!pop_host || !fit_host) return fail(h, DE_E_INVALID, "pop_host and fit_host are required");
+  if (gen < 0 || gen >= 0xFFFFFFFFll) return fail(h, DE_E_INVALID, "gen out of range");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const RunDev& R = h->host[run];
+  if (best_idx >= R.N) return fail(h, DE_E_INVALID, "best_idx out of range");
+  const size_t e = esz(R.dtype);
+  BestState B{};
+  B.g = static_cast<uint32_t>(gen);
+  if (best_idx >= 0) {
+    B.f = best_f;
+    B.idx = best_idx;
+    B.gen = best_gen;
+  } else {
+    int64_t m = 0;
+    double fm = 0.0;
+    for (int64_t i = 0; i < R.N; ++i) {
+      double v = R.dtype == DE_FP64 ? static_cast<const double*>(fit_host)[i]
+                                    : static_cast<double>(static_cast<const float*>(fit_host)[i]);
+      if (v != v) v = INFINITY;
+      if (i == 0 || v < fm) { fm = v; m = i; }
+    }
+    B.f = fm;
+    B.idx = m;
+    B.gen = gen;
+  }
+  HIPCHECK(h, hipMemcpy2DAsync(R.X[0], e * R.ld, pop_host, e * R.D, e * R.D, R.N,
+                               hipMemcpyHostToDevice, s));
+  HIPCHECK(h, hipMemcpyAsync(R.fit, fit_host, e * R.N, hipMemcpyHostToDevice, s));
+  HIPCHECK(h, de::launch_fill_u8(R.flags, 2 * R.N, 0, s));
+  HIPCHECK(h, hipMemcpyAsync(h->best + run, &B, sizeof B, hipMemcpyHostToDevice, s));
+  HIPCHECK(h, hipStreamSynchronize(s));
+  return DE_OK;
+}
+
+de_status de_trace(de_handle* h, int32_t run, int64_t* idx, uint8_t* mask, void* trial,
+                   void* ftrial) {
+  de_status st = check_run(h, run);
+  if (st != DE_OK) return st;
+  HIPCHECK(h, hipDeviceSynchronize());
+  RunDev& R = h->host[run];
+  R.tr_idx = idx;
+  R.tr_mask = mask;
+  R.tr_trial = trial;
+  R.tr_ftrial = ftrial;
+  HIPCHECK(h, hipMemcpy(h->dev_runs + run, &R, sizeof R, hipMemcpyHostToDevice));
+  return DE_OK;
+}
+
+de_status de_profile(de_handle* h, int32_t enable) {
+  if (!h) return fail(nullptr, DE_E_INVALID, "NULL handle");
+  h->prof = enable != 0;
+  h->ev_used = 0;
+  return DE_OK;
+}
+
+de_status de_profile_read(de_handle* h, double* main_ms, int64_t* main_launches) {
+  if (!h) return fail(nullptr, DE_E_INVALID, "NULL handle");
+  double total = 0.0;
+  int64_t n = 0;
+  for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+    HIPCHECK(h, hipEventSynchronize(h->ev_pool[k + 1]));
+    float ms = 0.0f;
+    HIPCHECK(h, hipEventElapsedTime(&ms, h->ev_pool[k], h->ev_pool[k + 1]));
+    total += ms;
+    ++n;
+  }
+  if (main_ms) *main_ms = total;
+  if (main_launches) *main_launches = n;
+  return DE_OK;
+}
+
+const char* de_last_error(const de_handle* h) {
+  if (h) return h->err.c_str();
+  return g_err.c_str();
+}
+
+void de_destroy(de_handle* h) {
+  if (!h) return;
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  delete h;
+}
+
+}  // extern "C"

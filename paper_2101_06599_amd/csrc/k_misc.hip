@@ -1,0 +1,383 @@
+// Supporting kernels: initial population and shift, whole-row fitness,
+// best-so-far tracking, the classic exponential crossover as one job per
+// individual, and state helpers.
+#include "de_device.h"
+
+namespace de {
+
+// ---- initialisation (Alg 2 lines 2-3) -------------------------------------
+
+// Uniform in [lo, hi]: FP64 takes 53 bits from two words of block j/2, FP32
+// takes 24 bits from word j%4 of block j/4.
+template <typename T>
+__device__ __forceinline__ T init_value(const RunDev& P, uint32_t tag, uint32_t i, uint32_t j,
+                                        double lo, double hi) {
+  if constexpr (sizeof(T) == 8) {
+    const uint4 b = draw(P, tag, 0, i, j >> 1);
+    const uint32_t a = (j & 1u) ? b.z : b.x;
+    const uint32_t c = (j & 1u) ? b.w : b.y;
+    const uint64_t bits = (static_cast<uint64_t>(a >> 5) << 26) | (c >> 6);
+    const double u = static_cast<double>(bits) * 0x1p-53;
+    return __builtin_fma(hi - lo, u, lo);
+  } else {
+    const uint4 b = draw(P, tag, 0, i, j >> 2);
+    const float u = static_cast<float>(word_of(b, j & 3u) >> 8) * 0x1p-24f;
+    const float lof = static_cast<float>(lo), hif = static_cast<float>(hi);
+    return __builtin_fmaf(hif - lof, u, lof);
+  }
+}
+
+// One thread per element of both population buffers (padding zeroed), plus
+// the shift vector in block row 0 and the flag arrays.
+template <typename T>
+__global__ void k_init(const RunDev* __restrict__ runs, int32_t run, double lo, double hi,
+                       double olo, double ohi, const T* __restrict__ shift_src, int gen_shift) {
+  const RunDev& P = runs[run];
+  const int64_t ld = P.ld, N = P.N, D = P.D;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < N * ld) {
+    const int64_t i = e / ld, j = e % ld;
+    const T v = j < D ? init_value<T>(P, TAG_INIT, static_cast<uint32_t>(i),
+                                      static_cast<uint32_t>(j), lo, hi)
+                      : T(0);
+    static_cast<T*>(P.X[0])[e] = v;
+    static_cast<T*>(P.X[1])[e] = T(0);
+  }
+  if (e < ld) {
+    T ov = T(0);
+    if (e < D) {
+      if (shift_src) ov = shift_src[e];
+      else if (gen_shift) ov = init_value<T>(P, TAG_SHIFT, 0, static_cast<uint32_t>(e), olo, ohi);
+    }
+    static_cast<T*>(const_cast<void*>(P.o))[e] = ov;
+  }
+  if (e < 2 * N) P.flags[e] = 0;
+}
+
+// ---- whole-row fitness ----------------------------------------------------
+
+template <typename T, int FN>
+__device__ __forceinline__ T elem_term(const T* x, const T* o, uint32_t j, uint32_t D) {
+  if constexpr (FN == FN_SPHERE) {
+    return point_term<T, FN_SPHERE>(x[j], T(0));
+  } else if constexpr (FN == FN_RASTRIGIN) {
+    return point_term<T, FN_RASTRIGIN>(x[j], o[j]);
+  } else {
+    if (j + 1 >= D) return T(0);
+    const T z0 = (x[j] - o[j]) + T(1);
+    const T z1 = (x[j + 1] - o[j + 1]) + T(1);
+    return rosen_term(z0, z1);
+  }
+}
+
+// f of one row with a 256-thread block (strided loop, fixed-order reduction).
+template <typename T, int FN>
+__device__ T block_row_fitness(const T* x, const T* o, uint32_t D) {
+  __shared__ T red[4];
+  T acc = T(0);
+  for (uint32_t j = threadIdx.x; j < D; j += blockDim.x) acc += elem_term<T, FN>(x, o, j, D);
+  acc = wave_sum(acc);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  return canon(red[0] + red[1] + red[2] + red[3]);
+}
+
+template <typename T>
+__device__ T block_row_fitness_rt(int fn, const T* x, const T* o, uint32_t D) {
+  if (fn == FN_SPHERE) return block_row_fitness<T, FN_SPHERE>(x, o, D);
+  if (fn == FN_RASTRIGIN) return block_row_fitness<T, FN_RASTRIGIN>(x, o, D);
+  return block_row_fitness<T, FN_ROSENBROCK>(x, o, D);
+}
+
+// Initial evaluation (Alg 2 line 3): rows of buffer 0.
+template <typename T>
+__global__ void __launch_bounds__(256) k_eval_pop(const RunDev* __restrict__ runs, int32_t run) {
+  const RunDev& P = runs[run];
+  const int64_t i = blockIdx.x;
+  const T* x = static_cast<const T*>(P.X[0]) + i * P.ld;
+  const T f = block_row_fitness_rt<T>(P.fn, x, static_cast<const T*>(P.o),
+                                      static_cast<uint32_t>(P.D));
+  if (threadIdx.x == 0) static_cast<T*>(P.fit)[i] = f;
+}
+
+// Caller rows (dense, pitch ldx) -> out.
+template <typename T>
+__global__ void __launch_bounds__(256) k_eval_rows(int fn, const T* __restrict__ X, int64_t ldx,
+                                                   const T* __restrict__ o, uint32_t D,
+                                                   T* __restrict__ out) {
+  const int64_t r = blockIdx.x;
+  const T f = block_row_fitness_rt<T>(fn, X + r * ldx, o, D);
+  if (threadIdx.x == 0) out[r] = f;
+}
+
+// Fitness of the trial each row left in its non-current buffer, then greedy
+// selection (used after the job-per-individual exponential crossover).
+template <typename T>
+__global__ void __launch_bounds__(256) k_eval_select(const RunDev* __restrict__ runs, int32_t run) {
+  const RunDev& P = runs[run];
+  const uint32_t i = blockIdx.x;
+  const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
+  const uint32_t g = P.best->g + 1;
+  const uint8_t* cur = P.flags + ((g - 1) & 1u) * static_cast<int64_t>(N);
+  uint8_t* nxt = P.flags + (g & 1u) * static_cast<int64_t>(N);
+  const uint32_t ci = cur[i];
+  const T* u = static_cast<const T*>(P.X[ci ^ 1u]) + static_cast<int64_t>(i) * P.ld;
+  const T fu = block_row_fitness_rt<T>(P.fn, u, static_cast<const T*>(P.o), D);
+  T* fit = static_cast<T*>(P.fit);
+  const bool win = fu < fit[i];
+  if (threadIdx.x == 0) {
+    nxt[i] = static_cast<uint8_t>(win ? ci ^ 1u : ci);
+    if (win) fit[i] = fu;
+    if (P.tr_idx) P.tr_idx[6 * static_cast<int64_t>(i) + 5] = win ? 1 : 0;
+    if (P.tr_ftrial) static_cast<T*>(P.tr_ftrial)[i] = fu;
+  }
+}
+
+// ---- classic exponential crossover, one job per individual (Alg 8) --------
+// One work-item builds individual i's whole trial: copy the parent (line 3),
+// then walk from j_rand taking the mutant element and drawing the next
+// uniform until a draw reaches Cr or the whole row is taken (lines 4-9).
+template <typename T>
+__global__ void __launch_bounds__(64) k_pexp_trial(const RunDev* __restrict__ runs, int32_t run) {
+  const RunDev& P = runs[run];
+  const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const uint32_t g = P.best->g + 1;
+  const int64_t ld = P.ld;
+  uint32_t r0, r1, r2;
+  pick_indices(draw(P, TAG_IDX, g, i, 0), N, i, r0, r1, r2);
+  const uint32_t jr = scale_index(draw(P, TAG_XO, g, i, 0).x, D);
+  const uint8_t* cur = P.flags + ((g - 1) & 1u) * static_cast<int64_t>(N);
+  const uint32_t ci = cur[i];
+  const T* xi = static_cast<const T*>(P.X[ci]) + static_cast<int64_t>(i) * ld;
+  const T* x0 = static_cast<const T*>(P.X[cur[r0]]) + static_cast<int64_t>(r0) * ld;
+  const T* x1 = static_cast<const T*>(P.X[cur[r1]]) + static_cast<int64_t>(r1) * ld;
+  const T* x2 = static_cast<const T*>(P.X[cur[r2]]) + static_cast<int64_t>(r2) * ld;
+  T* u = static_cast<T*>(P.X[ci ^ 1u]) + static_cast<int64_t>(i) * ld;
+  const T F = sizeof(T) == 4 ? static_cast<T>(P.Ff) : static_cast<T>(P.F);
+  for (uint32_t j = 0; j < D; ++j) u[j] = xi[j];
+  uint32_t j = jr, L = 0, e = 0;
+  uint4 b = make_uint4(0, 0, 0, 0);
+  bool more;
+  do {
+    u[j] = Math<T>::fma_(F, x1[j] - x2[j], x0[j]);
+    j = (j + 1 == D) ? 0 : j + 1;
+    ++L;
+    if ((e & 3u) == 0) b = draw(P, TAG_EXP, g, i, e >> 2);
+    more = static_cast<uint64_t>(word_of(b, e & 3u)) < P.thr && L < D;
+    ++e;
+  } while (more);
+  if (P.tr_idx) {
+    int64_t* q = P.tr_idx + 6 * static_cast<int64_t>(i);
+    q[0] = r0; q[1] = r1; q[2] = r2; q[3] = jr; q[4] = L; q[5] = 0;
+  }
+  if (P.tr_trial)
+    for (uint32_t s = 0; s < D; ++s) static_cast<T*>(P.tr_trial)[static_cast<int64_t>(i) * D + s] = u[s];
+  if (P.tr_mask)
+    for (uint32_t s = 0; s < D; ++s) {
+      const uint32_t off = s >= jr ? s - jr : s + D - jr;
+      P.tr_mask[static_cast<int64_t>(i) * D + s] = static_cast<uint8_t>(off < L);
+    }
+}
+
+// ---- best so far (Tables 3-5: best value, best gen) ------------------------
+// One block per run: argmin of the fitness (lowest index on ties); a strictly
+// better value than the best so far records the generation.  The block then
+// advances the run's generation count.
+template <typename T>
+__device__ void best_of_run(const RunDev& P, bool init) {
+  __shared__ T sf[256];
+  __shared__ int64_t si[256];
+  const int64_t N = P.N;
+  const T* fit = static_cast<const T*>(P.fit);
+  T bf = Math<T>::inf();
+  int64_t bi = N;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    const T f = fit[i];
+    if (bi == N || f < bf) {  // strict: the lowest index keeps a tie
+      bf = f;
+      bi = i;
+    }
+  }
+  sf[threadIdx.x] = bf;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const T f2 = sf[threadIdx.x + s];
+      const int64_t i2 = si[threadIdx.x + s];
+      const T f1 = sf[threadIdx.x];
+      const int64_t i1 = si[threadIdx.x];
+      if (i2 < N && (i1 >= N || f2 < f1 || (f2 == f1 && i2 < i1))) {
+        sf[threadIdx.x] = f2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    BestState* B = P.best;
+    const double fm = static_cast<double>(sf[0]);
+    const int64_t im = si[0] < N ? si[0] : 0;
+    if (init) {
+      B->f = fm;
+      B->idx = im;
+      B->gen = 0;
+      B->g = 0;
+    } else {
+      const uint32_t g = B->g + 1;
+      if (fm < B->f) {
+        B->f = fm;
+        B->idx = im;
+        B->gen = g;
+      }
+      B->g = g;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_best(const RunDev* __restrict__ runs, int init) {
+  const RunDev& P = runs[blockIdx.x];
+  if (P.dtype == 0) best_of_run<double>(P, init != 0);
+  else best_of_run<float>(P, init != 0);
+}
+
+// FP64 fitness of the best row, recomputed from the stored vector.
+template <typename T>
+__global__ void __launch_bounds__(256) k_best_fp64(const RunDev* __restrict__ runs, int32_t run,
+                                                   double* __restrict__ out) {
+  const RunDev& P = runs[run];
+  const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
+  const int64_t i = P.best->idx;
+  const uint8_t* cur = P.flags + (P.best->g & 1u) * static_cast<int64_t>(N);
+  const T* x = static_cast<const T*>(P.X[cur[i]]) + i * P.ld;
+  const T* o = static_cast<const T*>(P.o);
+  __shared__ double red[4];
+  double acc = 0.0;
+  if (P.fn == FN_ELLIPSOID) {
+    // z_k = sum_j M_kj (x_j - o_j) with the caller's FP64 M
+    for (uint32_t k = threadIdx.x; k < D; k += blockDim.x) {
+      double z = 0.0;
+      for (uint32_t j = 0; j < D; ++j)
+        z = __builtin_fma(P.rot[static_cast<int64_t>(k) * D + j],
+                          static_cast<double>(x[j]) - static_cast<double>(o[j]), z);
+      const double wk = static_cast<double>(static_cast<const T*>(P.w)[k]);
+      acc = __builtin_fma(wk * z, z, acc);
+    }
+  } else {
+    for (uint32_t j = threadIdx.x; j < D; j += blockDim.x) {
+      const double xj = static_cast<double>(x[j]);
+      const double oj = P.fn == FN_SPHERE ? 0.0 : static_cast<double>(o[j]);
+      if (P.fn == FN_SPHERE) acc += point_term<double, FN_SPHERE>(xj, 0.0);
+      else if (P.fn == FN_RASTRIGIN) acc += point_term<double, FN_RASTRIGIN>(xj, oj);
+      else if (j + 1 < D)
+        acc += rosen_term((xj - oj) + 1.0,
+                          (static_cast<double>(x[j + 1]) - static_cast<double>(o[j + 1])) + 1.0);
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = canon(red[0] + red[1] + red[2] + red[3]);
+}
+
+// ---- state helpers ---------------------------------------------------------
+
+// Move every row into buffer 0 (rows whose current copy is in buffer 1 are
+// copied back) and clear the current flags, so buffer 0 is the population.
+template <typename T>
+__global__ void __launch_bounds__(256) k_normalize(const RunDev* __restrict__ runs, int32_t run) {
+  const RunDev& P = runs[run];
+  const int64_t N = P.N, ld = P.ld;
+  const uint32_t g = P.best->g;
+  uint8_t* cur = P.flags + (g & 1u) * N;
+  const int64_t i = blockIdx.x;
+  if (cur[i] == 0) return;
+  const T* src = static_cast<const T*>(P.X[1]) + i * ld;
+  T* dst = static_cast<T*>(P.X[0]) + i * ld;
+  for (int64_t j = threadIdx.x; j < ld; j += blockDim.x) dst[j] = src[j];
+  __syncthreads();
+  if (threadIdx.x == 0) cur[i] = 0;
+}
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+// ---- launchers ---------------------------------------------------------------
+
+static inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
+
+hipError_t launch_init_impl(const RunDev* runs, const RunDev& h, int run, double lo, double hi,
+                            double olo, double ohi, const void* shift, hipStream_t s) {
+  const int64_t n = h.N * h.ld;
+  const int gen_shift = h.fn != FN_SPHERE && shift == nullptr;
+  if (h.dtype == 0)
+    hipLaunchKernelGGL(k_init<double>, dim3(nblk(n, 256)), dim3(256), 0, s, runs, run, lo, hi, olo,
+                       ohi, static_cast<const double*>(shift), gen_shift);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(nblk(n, 256)), dim3(256), 0, s, runs, run, lo, hi, olo,
+                       ohi, static_cast<const float*>(shift), gen_shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_pop(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
+  if (h.dtype == 0) hipLaunchKernelGGL(k_eval_pop<double>, dim3(h.N), dim3(256), 0, s, runs, run);
+  else hipLaunchKernelGGL(k_eval_pop<float>, dim3(h.N), dim3(256), 0, s, runs, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_rows(const RunDev& h, const void* X, int64_t rows, int64_t ldx, void* out,
+                            hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  if (h.dtype == 0)
+    hipLaunchKernelGGL(k_eval_rows<double>, dim3(rows), dim3(256), 0, s, h.fn,
+                       static_cast<const double*>(X), ldx, static_cast<const double*>(h.o),
+                       static_cast<uint32_t>(h.D), static_cast<double*>(out));
+  else
+    hipLaunchKernelGGL(k_eval_rows<float>, dim3(rows), dim3(256), 0, s, h.fn,
+                       static_cast<const float*>(X), ldx, static_cast<const float*>(h.o),
+                       static_cast<uint32_t>(h.D), static_cast<float*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_select(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
+  if (h.dtype == 0) hipLaunchKernelGGL(k_eval_select<double>, dim3(h.N), dim3(256), 0, s, runs, run);
+  else hipLaunchKernelGGL(k_eval_select<float>, dim3(h.N), dim3(256), 0, s, runs, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_pexp_trial(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
+  if (h.dtype == 0) hipLaunchKernelGGL(k_pexp_trial<double>, dim3(nblk(h.N, 64)), dim3(64), 0, s, runs, run);
+  else hipLaunchKernelGGL(k_pexp_trial<float>, dim3(nblk(h.N, 64)), dim3(64), 0, s, runs, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_best(const RunDev* runs, int n_runs, bool init, hipStream_t s) {
+  hipLaunchKernelGGL(k_best, dim3(n_runs), dim3(256), 0, s, runs, init ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_fp64(const RunDev* runs, const RunDev& h, int run, double* out,
+                            hipStream_t s) {
+  if (h.dtype == 0) hipLaunchKernelGGL(k_best_fp64<double>, dim3(1), dim3(256), 0, s, runs, run, out);
+  else hipLaunchKernelGGL(k_best_fp64<float>, dim3(1), dim3(256), 0, s, runs, run, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
+  if (h.dtype == 0) hipLaunchKernelGGL(k_normalize<double>, dim3(h.N), dim3(256), 0, s, runs, run);
+  else hipLaunchKernelGGL(k_normalize<float>, dim3(h.N), dim3(256), 0, s, runs, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u8, dim3(nblk(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace de

@@ -1,0 +1,418 @@
+// Rotated ellipsoid fitness f_i = sum_k w_k z_ik^2 with z_i = M (u_i - o):
+// the one dense contraction of the path, Z = (U - 1 o^T) M^T, an N x D x D
+// product with both operands contiguous along the contraction index.
+//
+// One kernel does the product on the matrix cores with the shift subtraction
+// (and, for the split-bf16 modes, the hi/mid/lo split of U - o) fused into the
+// A-tile load, and the weighted square sum fused into the epilogue, so Z is
+// never stored: each block writes one partial sum per row for its 128 output
+// columns.  A second kernel adds the partials of a row in a fixed order and
+// performs greedy selection.
+//
+// Modes: FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_16x16x4), and bf16
+// splits of both operands into 2 or 3 pieces whose 3 or 6 leading cross
+// products are accumulated in FP32 (v_mfma_f32_16x16x32_bf16).
+//
+// Lane layout of the 16x16 MFMA tiles used here (KPL = k values per lane:
+// 8 for bf16, 1 for f32/f64): lane l supplies A[l%16][(l/16)*KPL + e] and
+// B[(l/16)*KPL + e][l%16].  Accumulator register r of lane l holds
+// C[(l/16)*4 + r][l%16] for the f32/bf16 forms and C[4r + l/16][l%16] for
+// the f64 form (checked on gfx950 with integer-valued operands).
+#include <type_traits>
+
+#include "de_device.h"
+
+namespace de {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+enum : int { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3 };
+
+template <int MODE> struct MM;
+template <> struct MM<MM_FP64> {
+  using T = double; using L = double; static constexpr int P = 1, KT = 16, BM = 64, BN = 64, PAD = 2;
+};
+template <> struct MM<MM_FP32> {
+  using T = float; using L = float; static constexpr int P = 1, KT = 16, BM = 128, BN = 128, PAD = 4;
+};
+template <> struct MM<MM_BF16X3> {
+  using T = float; using L = __bf16; static constexpr int P = 2, KT = 32, BM = 128, BN = 128, PAD = 8;
+};
+template <> struct MM<MM_BF16X6> {
+  using T = float; using L = __bf16; static constexpr int P = 3, KT = 32, BM = 128, BN = 128, PAD = 8;
+};
+
+int rot_tile_n() { return 128; }  // BN of the FP32/bf16 modes; FP64 uses 64 (2 partials per 128)
+
+// Pieces of a value: hi = bf16(v), then the rounding remainders.
+__device__ __forceinline__ void split3(float v, __bf16& a, __bf16& b, __bf16& c) {
+  a = static_cast<__bf16>(v);
+  const float r1 = v - static_cast<float>(a);
+  b = static_cast<__bf16>(r1);
+  const float r2 = r1 - static_cast<float>(b);
+  c = static_cast<__bf16>(r2);
+}
+
+// Row source for the A operand.
+//   src 0: trials of the coming generation (non-current buffer of each row)
+//   src 1: current population
+//   src 2: staging rows (caller data for de_evaluate)
+template <typename T>
+__device__ __forceinline__ const T* a_row(const RunDev& P, int src, int64_t i) {
+  if (src == 2) return static_cast<const T*>(P.stage) + i * P.ld;
+  const uint32_t N = static_cast<uint32_t>(P.N);
+  const uint32_t g = P.best->g + (src == 0 ? 1u : 0u);
+  const uint8_t* cur = P.flags + ((src == 0 ? g - 1 : g) & 1u) * static_cast<int64_t>(N);
+  const uint32_t b = cur[i] ^ (src == 0 ? 1u : 0u);
+  return static_cast<const T*>(P.X[b]) + i * P.ld;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ runs, int32_t run,
+                                                 int src, int64_t rows) {
+  using C = MM<MODE>;
+  using T = typename C::T;
+  using LT = typename C::L;
+  constexpr int BM = C::BM, BN = C::BN, KT = C::KT, P = C::P, LDK = KT + C::PAD;
+  constexpr int WM = BM / 32, WN = BN / 32;  // 16x16 subtiles per wave (2x2 waves)
+  __shared__ __attribute__((aligned(16))) LT As[P][BM][LDK];
+  __shared__ __attribute__((aligned(16))) LT Bs[P][BN][LDK];
+  __shared__ T red[2][BM];
+
+  const RunDev& Pr = runs[run];
+  const int64_t D = Pr.D, ldk = Pr.ldk;
+  const int ntm = static_cast<int>((rows + BM - 1) / BM);
+  const int ntn = static_cast<int>((D + BN - 1) / BN);
+  // XCD-aware order: consecutive blocks go round-robin over the 8 XCDs, so
+  // hand each XCD a contiguous range of tiles (tiles of one row block share A).
+  const int nb = ntm * ntn;
+  int b = blockIdx.x;
+  if (nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
+  const int tm = b / ntn, tn = b % ntn;
+  const int64_t row0 = static_cast<int64_t>(tm) * BM, col0 = static_cast<int64_t>(tn) * BN;
+
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wm = wave / 2, wn = wave % 2;
+
+  // A-load assignment: each thread covers one row segment of the K tile.
+  constexpr int A_TPR = 256 / BM;            // threads per A row
+  constexpr int A_SEG = KT / A_TPR;          // values per thread
+  const int a_r = tid / A_TPR, a_k = (tid % A_TPR) * A_SEG;
+  const int64_t ai = min(row0 + a_r, rows - 1);
+  const T* arow = a_row<T>(Pr, src, ai);
+  const T* o = static_cast<const T*>(Pr.o);
+  // B-load assignment, same shape over the BN rows of M.
+  constexpr int B_TPR = 256 / BN;
+  constexpr int B_SEG = KT / B_TPR;
+  const int b_r = tid / B_TPR, b_k = (tid % B_TPR) * B_SEG;
+  const int64_t bn = col0 + b_r;  // rows of M pieces are padded to a multiple of 128
+
+  using Acc = typename std::conditional<MODE == MM_FP64, f64x4, f32x4>::type;
+  Acc acc[WM][WN];
+#pragma unroll
+  for (int m = 0; m < WM; ++m)
+#pragma unroll
+    for (int n = 0; n < WN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[m][n][r] = 0;
+
+  const int nk = static_cast<int>((D + KT - 1) / KT);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int64_t k0 = static_cast<int64_t>(kt) * KT;
+    // ---- global -> LDS ----
+#pragma unroll
+    for (int e = 0; e < A_SEG; ++e) {
+      const int64_t k = k0 + a_k + e;
+      const T a = arow[k] - o[k];  // padding columns hold zeros on both sides
+      if constexpr (P == 1) {
+        As[0][a_r][a_k + e] = a;
+      } else {
+        __bf16 h, m, l;
+        split3(a, h, m, l);
+        As[0][a_r][a_k + e] = h;
+        As[1][a_r][a_k + e] = m;
+        if constexpr (P == 3) As[2][a_r][a_k + e] = l;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const LT* brow = static_cast<const LT*>(Pr.B[p]) + bn * ldk + k0 + b_k;
+#pragma unroll
+      for (int e = 0; e < B_SEG; ++e) Bs[p][b_r][b_k + e] = brow[e];
+    }
+    __syncthreads();
+    // ---- LDS -> matrix cores ----
+    if constexpr (P == 1) {
+#pragma unroll
+      for (int s = 0; s < KT / 4; ++s) {
+        T af[WM], bf[WN];
+#pragma unroll
+        for (int m = 0; m < WM; ++m) af[m] = As[0][wm * (BM / 2) + m * 16 + lane % 16][4 * s + lane / 16];
+#pragma unroll
+        for (int n = 0; n < WN; ++n) bf[n] = Bs[0][wn * (BN / 2) + n * 16 + lane % 16][4 * s + lane / 16];
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+#pragma unroll
+          for (int n = 0; n < WN; ++n) {
+            if constexpr (MODE == MM_FP64)
+              acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m], bf[n], acc[m][n], 0, 0, 0);
+            else
+              acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[m], bf[n], acc[m][n], 0, 0, 0);
+          }
+      }
+    } else {
+      bf16x8 af[P][WM], bfr[P][WN];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+          af[p][m] = *reinterpret_cast<const bf16x8*>(
+              &As[p][wm * (BM / 2) + m * 16 + lane % 16][8 * (lane / 16)]);
+#pragma unroll
+        for (int n = 0; n < WN; ++n)
+          bfr[p][n] = *reinterpret_cast<const bf16x8*>(
+              &Bs[p][wn * (BN / 2) + n * 16 + lane % 16][8 * (lane / 16)]);
+      }
+#pragma unroll
+      for (int m = 0; m < WM; ++m)
+#pragma unroll
+        for (int n = 0; n < WN; ++n) {
+          // smallest products first
+          if constexpr (P == 3) {
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][m], bfr[0][n], acc[m][n], 0, 0, 0);
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][m], bfr[1][n], acc[m][n], 0, 0, 0);
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][m], bfr[2][n], acc[m][n], 0, 0, 0);
+          }
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][m], bfr[0][n], acc[m][n], 0, 0, 0);
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][m], bfr[1][n], acc[m][n], 0, 0, 0);
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][m], bfr[0][n], acc[m][n], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: sum_k w_k z_ik^2 over this block's columns ----
+  const T* w = static_cast<const T*>(Pr.w);
+  T rs[WM][4];
+#pragma unroll
+  for (int m = 0; m < WM; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rs[m][r] = T(0);
+#pragma unroll
+  for (int n = 0; n < WN; ++n) {
+    const int64_t k = col0 + wn * (BN / 2) + n * 16 + lane % 16;
+    const T wk = k < D ? w[k] : T(0);
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const T z = static_cast<T>(acc[m][n][r]);
+        rs[m][r] += wk * z * z;
+      }
+  }
+  // reduce over the 16 lanes that share a row (fixed butterfly order)
+#pragma unroll
+  for (int m = 0; m < WM; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      T v = rs[m][r];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      rs[m][r] = v;
+    }
+  if (lane % 16 == 0) {
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = MODE == MM_FP64 ? 4 * r + lane / 16 : (lane / 16) * 4 + r;
+        red[wn][wm * (BM / 2) + m * 16 + rr] = rs[m][r];
+      }
+  }
+  __syncthreads();
+  T* part = static_cast<T*>(Pr.part);
+  const int ntot = Pr.ntile;
+  for (int rr = tid; rr < BM; rr += 256) {
+    const int64_t i = row0 + rr;
+    if (i < rows) part[i * ntot + tn] = red[0][rr] + red[1][rr];
+  }
+}
+
+// Sum of the partials of row i in tile order.
+template <typename T>
+__device__ __forceinline__ T row_total(const RunDev& P, int64_t i, int ntn) {
+  const T* part = static_cast<const T*>(P.part) + i * P.ntile;
+  T f = T(0);
+  for (int t = 0; t < ntn; ++t) f += part[t];
+  return canon(f);
+}
+
+// Greedy selection on the trials of generation g (Alg 2 lines 11-14).
+template <typename T>
+__global__ void k_rot_select(const RunDev* __restrict__ runs, int32_t run, int ntn) {
+  const RunDev& P = runs[run];
+  const uint32_t N = static_cast<uint32_t>(P.N);
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const uint32_t g = P.best->g + 1;
+  const uint8_t* cur = P.flags + ((g - 1) & 1u) * static_cast<int64_t>(N);
+  uint8_t* nxt = P.flags + (g & 1u) * static_cast<int64_t>(N);
+  const uint32_t ci = cur[i];
+  const T fu = row_total<T>(P, i, ntn);
+  T* fit = static_cast<T*>(P.fit);
+  const bool win = fu < fit[i];
+  nxt[i] = static_cast<uint8_t>(win ? ci ^ 1u : ci);
+  if (win) fit[i] = fu;
+  if (P.tr_idx) P.tr_idx[6 * static_cast<int64_t>(i) + 5] = win ? 1 : 0;
+  if (P.tr_ftrial) static_cast<T*>(P.tr_ftrial)[i] = fu;
+}
+
+template <typename T>
+__global__ void k_rot_store(const RunDev* __restrict__ runs, int32_t run, int ntn, int64_t rows,
+                            T* __restrict__ out) {
+  const RunDev& P = runs[run];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  out[i] = row_total<T>(P, i, ntn);
+}
+
+// M pieces (rows padded to a multiple of 128, columns to ldk, zero filled)
+// and the weights 10^(6k/(D-1)).
+template <int MODE>
+__global__ void k_rot_prepare(RunDev Pr, int64_t rows_pad) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t D = Pr.D, ldk = Pr.ldk;
+  if (e < rows_pad * ldk) {
+    const int64_t n = e / ldk, k = e % ldk;
+    const double m = (n < D && k < D) ? Pr.rot[n * D + k] : 0.0;
+    if constexpr (MODE == MM_FP64) {
+      static_cast<double*>(const_cast<void*>(Pr.B[0]))[e] = m;
+    } else if constexpr (MODE == MM_FP32) {
+      static_cast<float*>(const_cast<void*>(Pr.B[0]))[e] = static_cast<float>(m);
+    } else {
+      // split the FP64 value directly: each remainder is exact in FP64
+      const __bf16 h = static_cast<__bf16>(static_cast<float>(m));
+      const double r1 = m - static_cast<double>(static_cast<float>(h));
+      const __bf16 md = static_cast<__bf16>(static_cast<float>(r1));
+      const double r2 = r1 - static_cast<double>(static_cast<float>(md));
+      const __bf16 l = static_cast<__bf16>(static_cast<float>(r2));
+      static_cast<__bf16*>(const_cast<void*>(Pr.B[0]))[e] = h;
+      static_cast<__bf16*>(const_cast<void*>(Pr.B[1]))[e] = md;
+      if (MODE == MM_BF16X6) static_cast<__bf16*>(const_cast<void*>(Pr.B[2]))[e] = l;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_rot_weights(T* w, int64_t D) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < D) w[k] = static_cast<T>(D > 1 ? pow(10.0, 6.0 * static_cast<double>(k) / static_cast<double>(D - 1)) : 1.0);
+}
+
+// Dense caller rows -> padded staging rows (zero padding).
+template <typename T>
+__global__ void k_rot_stage(T* __restrict__ dst, int64_t ld, const T* __restrict__ src, int64_t D,
+                            int64_t rows) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= rows * ld) return;
+  const int64_t i = e / ld, k = e % ld;
+  dst[e] = k < D ? src[i * D + k] : T(0);
+}
+
+static inline unsigned nb(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
+
+static int tile_n_of(int mode) { return mode == MM_FP64 ? MM<MM_FP64>::BN : 128; }
+static int tile_m_of(int mode) { return mode == MM_FP64 ? MM<MM_FP64>::BM : 128; }
+
+hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s) {
+  const int64_t rows_pad = (h.D + 127) / 128 * 128;
+  const int64_t n = rows_pad * h.ldk;
+  switch (h.mm) {
+    case MM_FP64: hipLaunchKernelGGL(k_rot_prepare<MM_FP64>, dim3(nb(n, 256)), dim3(256), 0, s, h, rows_pad); break;
+    case MM_FP32: hipLaunchKernelGGL(k_rot_prepare<MM_FP32>, dim3(nb(n, 256)), dim3(256), 0, s, h, rows_pad); break;
+    case MM_BF16X3: hipLaunchKernelGGL(k_rot_prepare<MM_BF16X3>, dim3(nb(n, 256)), dim3(256), 0, s, h, rows_pad); break;
+    case MM_BF16X6: hipLaunchKernelGGL(k_rot_prepare<MM_BF16X6>, dim3(nb(n, 256)), dim3(256), 0, s, h, rows_pad); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (h.dtype == 0)
+    hipLaunchKernelGGL(k_rot_weights<double>, dim3(nb(h.D, 256)), dim3(256), 0, s,
+                       static_cast<double*>(const_cast<void*>(h.w)), h.D);
+  else
+    hipLaunchKernelGGL(k_rot_weights<float>, dim3(nb(h.D, 256)), dim3(256), 0, s,
+                       static_cast<float*>(const_cast<void*>(h.w)), h.D);
+  return hipGetLastError();
+}
+
+static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, int64_t rows,
+                       hipStream_t s) {
+  const int bm = tile_m_of(h.mm), bn = tile_n_of(h.mm);
+  const int64_t blocks = ((rows + bm - 1) / bm) * ((h.D + bn - 1) / bn);
+  switch (h.mm) {
+    case MM_FP64: hipLaunchKernelGGL(k_rot_gemm<MM_FP64>, dim3(blocks), dim3(256), 0, s, runs, run, src, rows); break;
+    case MM_FP32: hipLaunchKernelGGL(k_rot_gemm<MM_FP32>, dim3(blocks), dim3(256), 0, s, runs, run, src, rows); break;
+    case MM_BF16X3: hipLaunchKernelGGL(k_rot_gemm<MM_BF16X3>, dim3(blocks), dim3(256), 0, s, runs, run, src, rows); break;
+    case MM_BF16X6: hipLaunchKernelGGL(k_rot_gemm<MM_BF16X6>, dim3(blocks), dim3(256), 0, s, runs, run, src, rows); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, bool trials,
+                              hipStream_t s) {
+  return gemm(runs, h, run, trials ? 0 : 1, h.N, s);
+}
+
+hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
+  const int ntn = static_cast<int>((h.D + tile_n_of(h.mm) - 1) / tile_n_of(h.mm));
+  if (h.dtype == 0) hipLaunchKernelGGL(k_rot_select<double>, dim3(nb(h.N, 256)), dim3(256), 0, s, runs, run, ntn);
+  else hipLaunchKernelGGL(k_rot_select<float>, dim3(nb(h.N, 256)), dim3(256), 0, s, runs, run, ntn);
+  return hipGetLastError();
+}
+
+hipError_t launch_rot_init_fit(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
+  hipError_t e = gemm(runs, h, run, 1, h.N, s);
+  if (e != hipSuccess) return e;
+  const int ntn = static_cast<int>((h.D + tile_n_of(h.mm) - 1) / tile_n_of(h.mm));
+  if (h.dtype == 0)
+    hipLaunchKernelGGL(k_rot_store<double>, dim3(nb(h.N, 256)), dim3(256), 0, s, runs, run, ntn, h.N,
+                       static_cast<double*>(h.fit));
+  else
+    hipLaunchKernelGGL(k_rot_store<float>, dim3(nb(h.N, 256)), dim3(256), 0, s, runs, run, ntn, h.N,
+                       static_cast<float*>(h.fit));
+  return hipGetLastError();
+}
+
+// Caller rows in chunks of N through the staging buffer.
+hipError_t launch_rot_eval_rows(const RunDev* runs, const RunDev& h, int run, const void* X,
+                                int64_t rows, void* out, hipStream_t s) {
+  const int ntn = static_cast<int>((h.D + tile_n_of(h.mm) - 1) / tile_n_of(h.mm));
+  const int64_t esz = h.dtype == 0 ? 8 : 4;
+  for (int64_t r0 = 0; r0 < rows; r0 += h.N) {
+    const int64_t n = rows - r0 < h.N ? rows - r0 : h.N;
+    const char* src = static_cast<const char*>(X) + r0 * h.D * esz;
+    char* dst = static_cast<char*>(out) + r0 * esz;
+    if (h.dtype == 0)
+      hipLaunchKernelGGL(k_rot_stage<double>, dim3(nb(n * h.ld, 256)), dim3(256), 0, s,
+                         static_cast<double*>(h.stage), h.ld, reinterpret_cast<const double*>(src), h.D, n);
+    else
+      hipLaunchKernelGGL(k_rot_stage<float>, dim3(nb(n * h.ld, 256)), dim3(256), 0, s,
+                         static_cast<float*>(h.stage), h.ld, reinterpret_cast<const float*>(src), h.D, n);
+    hipError_t e = gemm(runs, h, run, 2, n, s);
+    if (e != hipSuccess) return e;
+    if (h.dtype == 0)
+      hipLaunchKernelGGL(k_rot_store<double>, dim3(nb(n, 256)), dim3(256), 0, s, runs, run, ntn, n,
+                         reinterpret_cast<double*>(dst));
+    else
+      hipLaunchKernelGGL(k_rot_store<float>, dim3(nb(n, 256)), dim3(256), 0, s, runs, run, ntn, n,
+                         reinterpret_cast<float*>(dst));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace de

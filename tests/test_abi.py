@@ -1,0 +1,78 @@
+"""The C-ABI library loads on the CPU and exports every entry point that
+include/de.h declares; host-side argument checks work without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2101_06599_amd as de
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "de.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(de_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(de.LIB_PATH):
+        pytest.fail("libde.so is not built (run __graft_entry__.build())")
+    return de.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert set(names) == set(de.ABI_FUNCTIONS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def good(**kw):
+    d = dict(N=50, D=10, F=0.5, CR=0.9, xo="bin", fn="sphere", dtype="fp64")
+    d.update(kw)
+    return d
+
+
+def test_workspace_size_and_validation(lib):
+    n1 = de.workspace_size([good()])
+    n2 = de.workspace_size([good(N=100)])
+    assert 0 < n1 < n2
+    big = de.workspace_size([good(N=2048, D=1000, fn="rastrigin", olo=-4, ohi=4)])
+    assert big >= 2 * 2048 * 1024 * 8  # two padded FP64 population buffers
+    bad = [good(N=3), good(D=0), good(CR=1.5), good(CR=float("nan")), good(F=-1.0),
+           good(F=float("inf")), good(lo=1.0, hi=1.0), good(N=1 << 21)]
+    for b in bad:
+        with pytest.raises(de.DEError) as e:
+            de.workspace_size([b])
+        assert e.value.status == de.E_INVALID
+    with pytest.raises(de.DEError) as e:
+        de.workspace_size([good(fn="ellipsoid_rot", D=8, dtype="fp64", mm="fp32")])
+    assert e.value.status == de.E_INVALID  # rot missing
+    # mixed dtypes and rotated runs cannot be batched
+    with pytest.raises(de.DEError) as e:
+        de.workspace_size([good(), good(dtype="fp32")])
+    assert e.value.status == de.E_UNSUPPORTED
+
+
+def test_init_rejects_bad_workspace_without_touching_gpu(lib):
+    keep = []
+    arr = (de.RunDesc * 1)(de._desc(good(), keep))
+    h = C.c_void_p(0)
+    st = lib.de_init(C.byref(h), arr, 1, None, 0, None)
+    assert st == de.E_WORKSPACE and not h.value
+    st = lib.de_init(C.byref(h), arr, 1, C.c_void_p(256), 16, None)
+    assert st == de.E_WORKSPACE
+    st = lib.de_init(C.byref(h), arr, 1, C.c_void_p(257), 1 << 30, None)
+    assert st == de.E_WORKSPACE  # misaligned
+    assert b"aligned" in lib.de_last_error(None)
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    assert lib.de_generation(None, 1, None) == de.E_INVALID
+    assert lib.de_evaluate(None, 0, None, 0, None, None) == de.E_INVALID
+    assert lib.de_profile(None, 1) == de.E_INVALID
+    lib.de_destroy(None)

@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar:
+* integer work bit-exact: r0, r1, r2, j_rand, L, the crossover mask, and
+  every selection bit except near-ties (below);
+* trial vectors bit-exact (FP64 and FP32: both sides use one fused
+  multiply-add on the rounded difference, no other contraction);
+* fitness within tol * Phi, Phi = f on absolute sub-terms: tol = 1e-12 (FP64),
+  1e-5 (FP32), 1e-6 (rotated, split bf16 into 3 pieces), 1e-4 (2 pieces);
+* a selection bit may differ only where |f(u) - f(x)| <= tol * max(Phi); the
+  GPU is then re-synchronised from the oracle so a flip does not cascade.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import compare_generation, gpu_runs, oracle_run, rotation, tol_of
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2101_06599_amd as de
+    de.lib()
+    yield
+
+
+def DE(cfgs, rot=None):
+    import paper_2101_06599_amd as de
+    return de.DE(gpu_runs(cfgs, rot), device="cuda:0")
+
+
+def c1(xo, **kw):
+    d = dict(N=50, D=10, F=0.5, CR=0.9, xo=xo, fn="sphere", dtype="fp64", lo=-100.0, hi=100.0,
+             seed=0)
+    d.update(kw)
+    return d
+
+
+def rast(**kw):
+    d = dict(N=64, D=1000, F=0.5, CR=0.9, xo="nec", fn="rastrigin", dtype="fp64", lo=-5.12,
+             hi=5.12, olo=-4.0, ohi=4.0, seed=3)
+    d.update(kw)
+    return d
+
+
+def rosen(**kw):
+    d = dict(N=12, D=1037, F=0.5, CR=0.9, xo="bin", fn="rosenbrock", dtype="fp32", lo=-5.12,
+             hi=5.12, olo=-4.0, ohi=4.0, seed=5)
+    d.update(kw)
+    return d
+
+
+def run_parity(cfg, gens, rot=None):
+    gpu = DE([cfg], rot)
+    ref = oracle_run(cfg, rot=rot)
+    pop_g, fit_g, _ = gpu.state(0)
+    pop_r, fit_r, _ = ref.state()
+    assert np.array_equal(pop_g.astype(np.float64), pop_r), "initial population"
+    phi = oracle.fitness_phi(cfg["fn"], pop_r, ref.shift(), rot)
+    assert np.all(np.abs(fit_g - fit_r) <= tol_of(cfg) * phi), "initial fitness"
+    trace = gpu.trace(0)
+    flips = 0
+    for _ in range(gens):
+        flips += compare_generation(gpu, ref, cfg, rot=rot, trace=trace)
+    return gpu, ref, flips
+
+
+# ---- the sphere workload, D = 10, N = 50, 100 generations ---------------
+
+@pytest.mark.parametrize("xo,impl", [("bin", "lane"), ("exp", "lane"), ("exp", "scan"),
+                                     ("exp", "job"), ("nec", "lane")])
+def test_sphere_d10_100_generations(xo, impl):
+    cfg = c1(xo, exp_impl=impl)
+    gpu, ref, flips = run_parity(cfg, 100)
+    fb, ib, gb, xb = gpu.best(0)
+    rb, rib, rgb, rxb = ref.best()
+    assert flips == 0
+    assert (ib, gb) == (rib, rgb)
+    assert abs(fb - rb) <= 1e-12 * rb
+    assert np.array_equal(xb, rxb)
+
+
+# ---- shifted Rastrigin, D = 1000 ------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("xo,impl", [("nec", "lane"), ("bin", "lane"), ("exp", "lane"),
+                                     ("exp", "scan"), ("exp", "job")])
+def test_rastrigin_d1000(dtype, xo, impl):
+    run_parity(rast(dtype=dtype, xo=xo, exp_impl=impl), 4)
+
+
+@pytest.mark.parametrize("CR", [0.0, 0.2, 0.5, 1.0])
+def test_rastrigin_cr_extremes(CR):
+    for xo in ("bin", "exp", "nec"):
+        run_parity(rast(N=16, D=300, CR=CR, xo=xo, exp_impl="scan"), 3)
+
+
+# ---- shifted Rosenbrock: ragged rows on every row shape -------------------
+
+@pytest.mark.parametrize("D", [2, 3, 7, 1037, 4500, 17001])
+@pytest.mark.parametrize("xo", ["bin", "nec"])
+def test_rosenbrock_row_shapes(D, xo):
+    run_parity(rosen(D=D, xo=xo, N=8 if D > 4000 else 12), 2)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_rosenbrock_d1000(dtype):
+    run_parity(rosen(D=1000, N=40, dtype=dtype, xo="exp", exp_impl="scan"), 3)
+
+
+# ---- launch shape does not change results ----------------------------------
+
+@pytest.mark.parametrize("cfg", [rast(N=40, D=999, xo="bin"), rosen(D=1001, N=20, xo="nec")])
+def test_row_width_invariance(cfg, monkeypatch):
+    outs = []
+    for tpr in ("64", "256", "1024"):
+        monkeypatch.setenv("DE_TPR", tpr)
+        gpu = DE([cfg])
+        tr = gpu.trace(0)
+        gpu.generation(1)
+        outs.append((tr["idx"].cpu().numpy().copy(), tr["trial"].cpu().numpy().copy(),
+                     tr["ftrial"].cpu().numpy().astype(np.float64)))
+        gpu.close()
+    tol = tol_of(cfg)
+    for o in outs[1:]:
+        assert np.array_equal(o[0][:, :5], outs[0][0][:, :5])
+        assert np.array_equal(o[1], outs[0][1])
+        assert np.all(np.abs(o[2] - outs[0][2]) <= tol * np.abs(outs[0][2]))
+
+
+# ---- rotated ellipsoid on the matrix cores ---------------------------------
+
+def ell(mm, dtype, **kw):
+    d = dict(N=100, D=160, F=0.5, CR=0.9, xo="nec", fn="ellipsoid_rot", dtype=dtype, mm=mm,
+             lo=-100.0, hi=100.0, olo=-80.0, ohi=80.0, seed=7)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("mm,dtype", [("fp64", "fp64"), ("fp32", "fp32"), ("bf16x6", "fp32"),
+                                      ("bf16x3", "fp32")])
+@pytest.mark.parametrize("xo", ["nec", "bin"])
+def test_rotated_ellipsoid(mm, dtype, xo):
+    D = 160
+    rot = rotation(D, 0)
+    run_parity(ell(mm, dtype, xo=xo), 3, rot=rot)
+
+
+def test_rotated_ellipsoid_exp_job():
+    rot = rotation(96, 1)
+    run_parity(ell("fp32", "fp32", D=96, N=70, xo="exp", exp_impl="job"), 2, rot=rot)
+
+
+# ---- several runs in one launch --------------------------------------------
+
+def test_batched_runs_match_independent_oracles():
+    from paper_2101_06599_amd import synth
+    cfgs = synth.batch_table(n_runs=6, seed=1, max_D=300, max_N=60)
+    cfgs[1]["xo"] = "bin"
+    cfgs[2]["xo"] = "exp"
+    cfgs[2]["exp_impl"] = "scan"
+    cfgs[3]["D"] = 1500  # past the register cache of a 64-lane row
+    gpu = DE(cfgs)
+    refs = [oracle_run(c, run=r) for r, c in enumerate(cfgs)]
+    traces = [gpu.trace(r) for r in range(len(cfgs))]
+    for _ in range(3):
+        gpu.generation(1)
+        for r, c in enumerate(cfgs):
+            compare_generation(gpu, refs[r], c, run=r, trace=traces[r], stepped=True)
+
+
+# ---- other entry points -----------------------------------------------------
+
+@pytest.mark.parametrize("cfg", [rast(dtype="fp64"), rast(dtype="fp32", fn="rosenbrock"),
+                                 c1("bin")])
+def test_evaluate_matches_oracle(cfg):
+    import torch
+    gpu = DE([cfg])
+    ref = oracle_run(cfg)
+    rng = np.random.default_rng(0)
+    X = rng.uniform(-5, 5, (33, cfg["D"]))
+    dt = torch.float64 if cfg["dtype"] == "fp64" else torch.float32
+    Xd = torch.as_tensor(X, dtype=dt, device="cuda:0")
+    Xr = Xd.cpu().numpy().astype(np.float64)
+    f = gpu.evaluate(0, Xd).cpu().numpy().astype(np.float64)
+    o = ref.shift()
+    fr = oracle.fitness(cfg["fn"], Xr, o)
+    phi = oracle.fitness_phi(cfg["fn"], Xr, o)
+    assert np.all(np.abs(f - fr) <= tol_of(cfg) * phi)
+    if cfg["fn"] != "sphere":  # the shift is the oracle's to the last bit
+        f0 = gpu.evaluate(0, torch.as_tensor(o, dtype=dt, device="cuda:0")[None, :])
+        assert float(f0.cpu()[0]) == 0.0
+
+
+def test_evaluate_rotated():
+    import torch
+    D = 200
+    rot = rotation(D, 2)
+    for mm, dtype in (("fp64", "fp64"), ("fp32", "fp32"), ("bf16x6", "fp32")):
+        cfg = ell(mm, dtype, D=D, N=50)
+        gpu = DE([cfg], rot)
+        ref = oracle_run(cfg, rot=rot)
+        X = np.random.default_rng(1).uniform(-100, 100, (130, D))
+        dt = torch.float64 if dtype == "fp64" else torch.float32
+        Xd = torch.as_tensor(X, dtype=dt, device="cuda:0")
+        Xr = Xd.cpu().numpy().astype(np.float64)
+        f = gpu.evaluate(0, Xd).cpu().numpy().astype(np.float64)
+        fr = oracle.fitness("ellipsoid_rot", Xr, ref.shift(), rot)
+        assert np.all(np.abs(f - fr) <= tol_of(cfg) * fr), mm
+
+
+def test_best_is_fp64_recompute_of_best_row():
+    cfg = rast(dtype="fp32", N=40, D=200)
+    gpu = DE([cfg])
+    gpu.generation(5)
+    f, idx, g, x = gpu.best(0)
+    pop, fit, gen = gpu.state(0)
+    assert gen == 5 and 0 <= g <= 5
+    assert np.array_equal(pop[idx], x)
+    assert fit[idx] == fit.min()
+    ref = oracle_run(cfg)
+    fr = oracle.fitness("rastrigin", x.astype(np.float64), ref.shift())
+    assert abs(f - fr) <= 1e-12 * fr
+
+
+def test_determinism_and_resume():
+    cfg = rast(N=50, D=500, xo="bin", dtype="fp32")
+    a = DE([cfg])
+    a.generation(12)
+    b = DE([cfg])
+    b.generation(5)
+    pop, fit, g = b.state(0)
+    fb, ib, gb, _ = b.best(0)
+    c = DE([cfg])
+    _, _, _ = c.state(0)
+    fbest_stored = float(fit[ib])
+    c.set_state(0, pop, fit, g, fbest_stored, ib, gb)
+    c.generation(7)
+    pa, fa, ga = a.state(0)
+    pc, fc, gc = c.state(0)
+    assert ga == gc == 12
+    assert np.array_equal(pa, pc) and np.array_equal(fa, fc)
+    assert a.best(0)[1:3] == c.best(0)[1:3]
+
+
+# ---- full sizes, launch shapes of the benchmark, sampled rows ---------------
+
+def sampled_rows(cfg, gens=1, n_sample=24, rot=None, seed=0):
+    """Run `gens` generations at full size; check sampled rows of the last
+    generation against the oracle's single-individual computation."""
+    gpu = DE([cfg], rot)
+    ref = oracle_run(cfg, rot=rot, lazy=True)
+    if gens > 1:
+        gpu.generation(gens - 1)
+    pop_before, fit_before, g0 = gpu.state(0)
+    tr = gpu.trace(0)
+    gpu.generation(1)
+    import torch
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(seed).choice(cfg["N"], n_sample, replace=False)
+    gi = tr["idx"].cpu().numpy()
+    o = ref.shift()
+    tol = tol_of(cfg)
+    P = pop_before.astype(np.float64)
+    for i in rows:
+        r = ref.individual(P, g0 + 1, int(i))
+        assert np.array_equal(gi[i, :5], r["idx"][:5]), (i, gi[i], r["idx"])
+        assert np.array_equal(tr["mask"][int(i)].cpu().numpy(), r["mask"])
+        gt = tr["trial"][int(i)].cpu().numpy().astype(np.float64)
+        assert np.array_equal(gt, r["trial"])
+        gf = float(tr["ftrial"][int(i)].cpu())
+        phi = oracle.fitness_phi(cfg["fn"], r["trial"], o, rot)
+        assert abs(gf - r["ftrial"]) <= tol * phi, (i, gf, r["ftrial"])
+        win = gi[i, 5] == 1
+        if abs(r["ftrial"] - float(fit_before[i])) > tol * phi:
+            assert win == (r["ftrial"] < float(fit_before[i]))
+    pop_after, fit_after, g1 = gpu.state(0)
+    assert g1 == g0 + 1
+    assert np.all(fit_after <= fit_before)
+    return gpu
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("xo", ["nec", "bin", "exp"])
+def test_full_size_rastrigin_2048x1000(dtype, xo):
+    from paper_2101_06599_amd import synth
+    cfg = dict(synth.RASTRIGIN_D1000, dtype=dtype, xo=xo, exp_impl="scan")
+    sampled_rows(cfg, gens=3)
+
+
+@pytest.mark.parametrize("xo", ["nec", "bin"])
+def test_full_size_rosenbrock_8192x10000(xo):
+    from paper_2101_06599_amd import synth
+    cfg = dict(synth.ROSENBROCK_D10000, xo=xo)
+    sampled_rows(cfg, gens=2, n_sample=12)
+
+
+@pytest.mark.parametrize("mm,dtype", [("bf16x6", "fp32"), ("fp32", "fp32"), ("fp64", "fp64")])
+def test_full_size_rotated_4096x2048(mm, dtype):
+    from paper_2101_06599_amd import synth
+    cfg = dict(synth.ELLIPSOID_D2048, mm=mm, dtype=dtype, xo="nec")
+    sampled_rows(cfg, gens=2, n_sample=6, rot=rotation(2048, 0))
