@@ -152,7 +152,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections", default="all",
-                    help="comma list of: variants,rosenbrock,rotated,batched,cpu (default all)")
+                    help="comma list of: head (headline only), variants, rosenbrock, rotated, "
+                         "batched, cpu, copy (default: all but copy)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -257,6 +258,17 @@ def main():
             "pop_dim_gen_s": elems * kb / (ms / 1e3),
             "hbm_frac_kernel": byt / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         g2.close()
+
+    if "copy" in secs:
+        # counter calibration: a plain device copy of a known size
+        n = 256 << 20
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read_per_copy": n, "bytes_written_per_copy": n,
+                                   "copies": 5}
 
     if "cpu" in secs:
         out["cpu_baseline"] = cpu_baseline(head, args.cpu_seconds)

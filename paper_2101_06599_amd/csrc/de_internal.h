@@ -14,15 +14,25 @@ enum : int { XO_BIN = 0, XO_EXP = 1, XO_NEC = 2, XO_ANY = -1 };
 enum : int { EXPI_LANE = 0, EXPI_JOB = 1, EXPI_SCAN = 2 };
 enum : uint32_t { TAG_INIT = 1, TAG_SHIFT = 2, TAG_IDX = 3, TAG_XO = 4, TAG_BIN = 5, TAG_EXP = 6 };
 
-// Per-run mutable scalars.  `gen` counts completed generations; the kernels
-// of generation g = gen + 1 read it and the last kernel of the generation
-// advances it, so graph replays need no host involvement.
+// Best so far of one run, as of generation g.  Kernels of a generation get
+// the handle's generation number as an argument (the host knows it without
+// asking the device); a run's own number is that plus its gen_offset.
 struct alignas(32) BestState {
   double f;       // best fitness so far (stored precision promoted to FP64)
   int64_t idx;    // row of the best individual
   int64_t gen;    // generation that found it
-  uint32_t g;     // completed generations
+  uint32_t g;     // generation the record is up to date with
   uint32_t pad;
+};
+
+// Generations whose best-so-far update is deferred: every row writes its
+// post-selection fitness (winners) or +inf (others) into slot g % kHist of a
+// ring, and one pass over up to kHist generations updates the BestState.
+constexpr int kHist = 64;
+
+struct alignas(16) GenMin {
+  double f;
+  int64_t idx;
 };
 
 struct alignas(64) RunDev {
@@ -39,6 +49,9 @@ struct alignas(64) RunDev {
   const void* o;          // shift, ld values (dtype), zero padded
   const uint64_t* T;      // NEC thresholds, T[k] for k = 0..D+1
   BestState* best;
+  int64_t gen_offset;     // run generation = handle generation + gen_offset
+  void* hist;             // kHist x N winner fitness (dtype), +inf for losers
+  GenMin* mins;           // kHist per-generation minima of this run
   // rotated function
   const double* rot;      // caller's FP64 M, D x D row-major
   const void* w;          // D weights (dtype)
@@ -62,29 +75,41 @@ struct GenLaunch {
   const uint2* rowmap;    // batched: global row -> (run, row)
   int64_t rows;           // rows in this launch
   int32_t tpr;            // threads per row
+  uint32_t gnew;          // handle generation being computed
   hipStream_t s;
 };
+
+__host__ __device__ inline uint32_t run_gen(const RunDev& P, uint32_t gnew) {
+  return static_cast<uint32_t>(static_cast<int64_t>(gnew) + P.gen_offset);
+}
 
 hipError_t launch_init_impl(const RunDev* runs, const RunDev& h, int run, double lo, double hi,
                             double olo, double ohi, const void* shift, hipStream_t s);
 hipError_t launch_eval_pop(const RunDev* runs, const RunDev& h, int run, hipStream_t s);
-hipError_t launch_best(const RunDev* runs, int n_runs, bool init, hipStream_t s);
+hipError_t launch_best_init(const RunDev* runs, int n_runs, hipStream_t s);
+// best-so-far over the deferred generations [gfirst, gfirst + count)
+hipError_t launch_best_flush(const RunDev* runs, int n_runs, int64_t max_rows, uint32_t gfirst,
+                             int count, hipStream_t s);
 hipError_t launch_generation(const GenLaunch& L, int fn, int xo, int dtype, bool batched);
-hipError_t launch_pexp_trial(const RunDev* runs, const RunDev& h, int run, hipStream_t s);
-hipError_t launch_eval_select(const RunDev* runs, const RunDev& h, int run, hipStream_t s);
+hipError_t launch_pexp_trial(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+                             hipStream_t s);
+hipError_t launch_eval_select(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+                              hipStream_t s);
 hipError_t launch_eval_rows(const RunDev& h, const void* X, int64_t rows, int64_t ldx, void* out,
                             hipStream_t s);
-hipError_t launch_best_fp64(const RunDev* runs, const RunDev& h, int run, double* out,
+hipError_t launch_best_fp64(const RunDev* runs, const RunDev& h, int run, uint32_t gcur,
+                            double* out, hipStream_t s);
+hipError_t launch_normalize(const RunDev* runs, const RunDev& h, int run, uint32_t gcur,
                             hipStream_t s);
-hipError_t launch_normalize(const RunDev* runs, const RunDev& h, int run, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
 // rotated function: M pieces and weights from the caller's FP64 M; fitness of
 // N rows (the trials of the coming generation when `trials`, else the
 // population) into fit_dst or, when select, straight into greedy selection.
 hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s);
-hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, bool trials,
+hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
                               hipStream_t s);
-hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, hipStream_t s);
+hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+                             hipStream_t s);
 hipError_t launch_rot_init_fit(const RunDev* runs, const RunDev& h, int run, hipStream_t s);
 hipError_t launch_rot_eval_rows(const RunDev* runs, const RunDev& h, int run, const void* X,
                                 int64_t rows, void* out, hipStream_t s);

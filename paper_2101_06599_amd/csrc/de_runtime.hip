@@ -31,6 +31,8 @@ struct de_handle {
   std::vector<uint2> rowmap_host;
   std::vector<std::vector<uint64_t>> tables;  // host copies of the NEC tables
   std::vector<int> tpr;
+  uint32_t done = 0;                 // generations completed by the handle
+  int pending = 0;                   // of which the best-so-far is not yet updated
   std::string err;
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -80,7 +82,7 @@ struct Layout {
   size_t total = 0;
   size_t runs_off = 0, best_off = 0, scratch_off = 0, rowmap_off = 0;
   struct Run {
-    size_t X0, X1, fit, flags, o, T, w, B[3], part, stage;
+    size_t X0, X1, fit, flags, o, T, hist, mins, w, B[3], part, stage;
     int64_t ld, ldk, ntile;
   };
   std::vector<Run> r;
@@ -167,6 +169,8 @@ Layout layout(const de_run_desc* runs, int32_t n_runs) {
     q.flags = bump(cur, 2 * d.N);
     q.o = bump(cur, s * q.ld);
     q.T = bump(cur, 8 * (d.D + 2));
+    q.hist = bump(cur, s * d.N * de::kHist);
+    q.mins = bump(cur, sizeof(de::GenMin) * de::kHist);
     q.ldk = 0;
     q.ntile = 0;
     q.w = q.part = q.stage = 0;
@@ -211,20 +215,29 @@ hipEvent_t next_event(de_handle* h) {
   return h->ev_pool[h->ev_used++];
 }
 
+// Best-so-far over the generations run since the last update.
+de_status flush_best(de_handle* h, hipStream_t s) {
+  if (h->pending == 0) return DE_OK;
+  const uint32_t gfirst = h->done - static_cast<uint32_t>(h->pending) + 1;
+  HIPCHECK(h, de::launch_best_flush(h->dev_runs, h->n_runs, 0, gfirst, h->pending, s));
+  h->pending = 0;
+  return DE_OK;
+}
+
 // The launches of one generation of one run (single-run handles) or of all
-// runs (batched); `main` brackets the dominant kernel with events if enabled.
+// runs (batched); `mark` brackets the dominant kernel with events if enabled.
 de_status one_generation(de_handle* h, hipStream_t s) {
-  auto mark = [&](bool on) -> hipEvent_t {
-    if (!h->prof || !on) return nullptr;
+  auto mark = [&]() {
+    if (!h->prof) return;
     hipEvent_t e = next_event(h);
     if (e) (void)hipEventRecord(e, s);
-    return e;
   };
+  const uint32_t gnew = h->done + 1;
   if (h->batched) {
-    de::GenLaunch L{h->dev_runs, h->host.data(), 0, h->rowmap, h->total_rows, 64, s};
-    mark(true);
+    de::GenLaunch L{h->dev_runs, h->host.data(), 0, h->rowmap, h->total_rows, 64, gnew, s};
+    mark();
     HIPCHECK(h, de::launch_generation(L, de::FN_ANY, de::XO_ANY, h->dtype, true));
-    mark(true);
+    mark();
   } else {
     for (int r = 0; r < h->n_runs; ++r) {
       const de_run_desc& d = h->desc[r];
@@ -232,29 +245,30 @@ de_status one_generation(de_handle* h, hipStream_t s) {
       const bool job = d.xo == DE_XO_EXP && d.exp_impl == DE_EXP_JOB;
       if (d.fn == DE_FN_ELLIPSOID_ROT) {
         if (job) {
-          HIPCHECK(h, de::launch_pexp_trial(h->dev_runs, H, r, s));
+          HIPCHECK(h, de::launch_pexp_trial(h->dev_runs, H, r, gnew, s));
         } else {
-          de::GenLaunch L{h->dev_runs, h->host.data(), r, nullptr, d.N, h->tpr[r], s};
+          de::GenLaunch L{h->dev_runs, h->host.data(), r, nullptr, d.N, h->tpr[r], gnew, s};
           HIPCHECK(h, de::launch_generation(L, de::FN_NONE, d.xo, d.dtype, false));
         }
-        mark(true);
-        HIPCHECK(h, de::launch_rot_fitness(h->dev_runs, H, r, true, s));
-        mark(true);
-        HIPCHECK(h, de::launch_rot_select(h->dev_runs, H, r, s));
+        mark();
+        HIPCHECK(h, de::launch_rot_fitness(h->dev_runs, H, r, gnew, s));
+        mark();
+        HIPCHECK(h, de::launch_rot_select(h->dev_runs, H, r, gnew, s));
       } else if (job) {
-        mark(true);
-        HIPCHECK(h, de::launch_pexp_trial(h->dev_runs, H, r, s));
-        mark(true);
-        HIPCHECK(h, de::launch_eval_select(h->dev_runs, H, r, s));
+        mark();
+        HIPCHECK(h, de::launch_pexp_trial(h->dev_runs, H, r, gnew, s));
+        mark();
+        HIPCHECK(h, de::launch_eval_select(h->dev_runs, H, r, gnew, s));
       } else {
-        de::GenLaunch L{h->dev_runs, h->host.data(), r, nullptr, d.N, h->tpr[r], s};
-        mark(true);
+        de::GenLaunch L{h->dev_runs, h->host.data(), r, nullptr, d.N, h->tpr[r], gnew, s};
+        mark();
         HIPCHECK(h, de::launch_generation(L, d.fn, d.xo, d.dtype, false));
-        mark(true);
+        mark();
       }
     }
   }
-  HIPCHECK(h, de::launch_best(h->dev_runs, h->n_runs, false, s));
+  h->done = gnew;
+  if (++h->pending == de::kHist) return flush_best(h, s);
   return DE_OK;
 }
 
@@ -324,6 +338,9 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
     R.o = ws + q.o;
     R.T = reinterpret_cast<const uint64_t*>(ws + q.T);
     R.best = h->best + r;
+    R.gen_offset = 0;
+    R.hist = ws + q.hist;
+    R.mins = reinterpret_cast<de::GenMin*>(ws + q.mins);
     if (d.fn == DE_FN_ELLIPSOID_ROT) {
       R.rot = d.rot;
       R.w = ws + q.w;
@@ -383,7 +400,7 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
       HIPINIT(de::launch_eval_pop(h->dev_runs, R, r, s));
     }
   }
-  HIPINIT(de::launch_best(h->dev_runs, n_runs, true, s));
+  HIPINIT(de::launch_best_init(h->dev_runs, n_runs, s));
   // host tables must outlive the asynchronous copies
   HIPINIT(hipStreamSynchronize(s));
 #undef HIPINIT
@@ -395,11 +412,13 @@ de_status de_generation(de_handle* h, int32_t n_gens, void* stream) {
   if (!h) return fail(nullptr, DE_E_INVALID, "NULL handle");
   if (n_gens < 0) return fail(h, DE_E_INVALID, "n_gens must be >= 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (static_cast<uint64_t>(h->done) + static_cast<uint64_t>(n_gens) >= 0xFFFFFFF0ull)
+    return fail(h, DE_E_STATE, "generation counter would overflow");
   for (int32_t k = 0; k < n_gens; ++k) {
     de_status st = one_generation(h, s);
     if (st != DE_OK) return st;
   }
-  return DE_OK;
+  return flush_best(h, s);
 }
 
 de_status de_evaluate(de_handle* h, int32_t run, const void* X, int64_t rows, void* fit_out,
@@ -425,7 +444,9 @@ de_status de_best(de_handle* h, int32_t run, double* f_best, int64_t* idx, int64
   if (st != DE_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const RunDev& R = h->host[run];
-  HIPCHECK(h, de::launch_best_fp64(h->dev_runs, R, run, h->scratch_f64, s));
+  st = flush_best(h, s);
+  if (st != DE_OK) return st;
+  HIPCHECK(h, de::launch_best_fp64(h->dev_runs, R, run, h->done, h->scratch_f64, s));
   BestState B;
   double f = 0.0;
   HIPCHECK(h, hipMemcpyAsync(&B, h->best + run, sizeof B, hipMemcpyDeviceToHost, s));
@@ -454,8 +475,10 @@ de_status de_get_state(de_handle* h, int32_t run, void* pop_host, void* fit_host
   hipStream_t s = static_cast<hipStream_t>(stream);
   const RunDev& R = h->host[run];
   const size_t e = esz(R.dtype);
+  st = flush_best(h, s);
+  if (st != DE_OK) return st;
   if (pop_host) {
-    HIPCHECK(h, de::launch_normalize(h->dev_runs, R, run, s));
+    HIPCHECK(h, de::launch_normalize(h->dev_runs, R, run, h->done, s));
     HIPCHECK(h, hipMemcpy2DAsync(pop_host, e * R.D, R.X[0], e * R.ld, e * R.D, R.N,
                                  hipMemcpyDeviceToHost, s));
   }
@@ -463,7 +486,7 @@ de_status de_get_state(de_handle* h, int32_t run, void* pop_host, void* fit_host
   BestState B;
   HIPCHECK(h, hipMemcpyAsync(&B, h->best + run, sizeof B, hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipStreamSynchronize(s));
-  if (gen) *gen = B.g;
+  if (gen) *gen = static_cast<int64_t>(h->done) + R.gen_offset;
   return DE_OK;
 }
 
@@ -475,8 +498,11 @@ de_status de_set_state(de_handle* h, int32_t run, const void* pop_host, const vo
   if (!pop_host || !fit_host) return fail(h, DE_E_INVALID, "pop_host and fit_host are required");
   if (gen < 0 || gen >= 0xFFFFFFFFll) return fail(h, DE_E_INVALID, "gen out of range");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const RunDev& R = h->host[run];
+  RunDev& R = h->host[run];
   if (best_idx >= R.N) return fail(h, DE_E_INVALID, "best_idx out of range");
+  st = flush_best(h, s);
+  if (st != DE_OK) return st;
+  R.gen_offset = gen - static_cast<int64_t>(h->done);
   const size_t e = esz(R.dtype);
   BestState B{};
   B.g = static_cast<uint32_t>(gen);
@@ -502,6 +528,7 @@ de_status de_set_state(de_handle* h, int32_t run, const void* pop_host, const vo
   HIPCHECK(h, hipMemcpyAsync(R.fit, fit_host, e * R.N, hipMemcpyHostToDevice, s));
   HIPCHECK(h, de::launch_fill_u8(R.flags, 2 * R.N, 0, s));
   HIPCHECK(h, hipMemcpyAsync(h->best + run, &B, sizeof B, hipMemcpyHostToDevice, s));
+  HIPCHECK(h, upload_run(h, run, s));
   HIPCHECK(h, hipStreamSynchronize(s));
   return DE_OK;
 }

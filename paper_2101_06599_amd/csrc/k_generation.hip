@@ -152,7 +152,7 @@ template <int TPR> struct Shape {
 template <typename T, int FN, int XO, int TPR, int MAXIT, bool BATCH>
 __global__ void __launch_bounds__(Shape<TPR>::BS)
 k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* __restrict__ rowmap,
-             int64_t rows) {
+             int64_t rows, uint32_t gnew) {
   using S = Shape<TPR>;
   __shared__ T red[S::RPB * S::NW];
   __shared__ uint32_t redc[S::RPB * S::NW];
@@ -179,7 +179,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   R.D = static_cast<uint32_t>(P.D);
   R.thr = P.thr;
   R.i = i;
-  R.g = P.best->g + 1;
+  R.g = run_gen(P, gnew);
   R.F = sizeof(T) == 4 ? static_cast<T>(P.Ff) : static_cast<T>(P.F);
   const uint32_t N = static_cast<uint32_t>(P.N);
   const int64_t ld = P.ld;
@@ -309,6 +309,9 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
     if (t == 0) {
       nxt[i] = static_cast<uint8_t>(win ? ci ^ 1u : ci);
       if (win) fit[i] = fu;
+      // deferred best-so-far: winners' new fitness, +inf for the others
+      static_cast<T*>(P.hist)[static_cast<int64_t>(gnew % kHist) * N + i] =
+          win ? fu : Math<T>::inf();
     }
   }
 
@@ -343,10 +346,10 @@ static hipError_t go(const GenLaunch& L, bool batched) {
   if (blocks <= 0) return hipSuccess;
   if (batched)
     hipLaunchKernelGGL((k_generation<T, FN, XO, TPR, 4, true>), dim3(blocks), dim3(S::BS), 0, L.s,
-                       L.runs, L.run, L.rowmap, L.rows);
+                       L.runs, L.run, L.rowmap, L.rows, L.gnew);
   else
     hipLaunchKernelGGL((k_generation<T, FN, XO, TPR, 4, false>), dim3(blocks), dim3(S::BS), 0, L.s,
-                       L.runs, L.run, L.rowmap, L.rows);
+                       L.runs, L.run, L.rowmap, L.rows, L.gnew);
   return hipGetLastError();
 }
 

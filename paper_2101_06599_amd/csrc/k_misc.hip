@@ -114,11 +114,12 @@ __global__ void __launch_bounds__(256) k_eval_rows(int fn, const T* __restrict__
 // Fitness of the trial each row left in its non-current buffer, then greedy
 // selection (used after the job-per-individual exponential crossover).
 template <typename T>
-__global__ void __launch_bounds__(256) k_eval_select(const RunDev* __restrict__ runs, int32_t run) {
+__global__ void __launch_bounds__(256) k_eval_select(const RunDev* __restrict__ runs, int32_t run,
+                                                     uint32_t gnew) {
   const RunDev& P = runs[run];
   const uint32_t i = blockIdx.x;
   const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
-  const uint32_t g = P.best->g + 1;
+  const uint32_t g = run_gen(P, gnew);
   const uint8_t* cur = P.flags + ((g - 1) & 1u) * static_cast<int64_t>(N);
   uint8_t* nxt = P.flags + (g & 1u) * static_cast<int64_t>(N);
   const uint32_t ci = cur[i];
@@ -129,6 +130,7 @@ __global__ void __launch_bounds__(256) k_eval_select(const RunDev* __restrict__ 
   if (threadIdx.x == 0) {
     nxt[i] = static_cast<uint8_t>(win ? ci ^ 1u : ci);
     if (win) fit[i] = fu;
+    static_cast<T*>(P.hist)[static_cast<int64_t>(gnew % kHist) * N + i] = win ? fu : Math<T>::inf();
     if (P.tr_idx) P.tr_idx[6 * static_cast<int64_t>(i) + 5] = win ? 1 : 0;
     if (P.tr_ftrial) static_cast<T*>(P.tr_ftrial)[i] = fu;
   }
@@ -139,12 +141,13 @@ __global__ void __launch_bounds__(256) k_eval_select(const RunDev* __restrict__ 
 // then walk from j_rand taking the mutant element and drawing the next
 // uniform until a draw reaches Cr or the whole row is taken (lines 4-9).
 template <typename T>
-__global__ void __launch_bounds__(64) k_pexp_trial(const RunDev* __restrict__ runs, int32_t run) {
+__global__ void __launch_bounds__(64) k_pexp_trial(const RunDev* __restrict__ runs, int32_t run,
+                                                   uint32_t gnew) {
   const RunDev& P = runs[run];
   const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const uint32_t g = P.best->g + 1;
+  const uint32_t g = run_gen(P, gnew);
   const int64_t ld = P.ld;
   uint32_t r0, r1, r2;
   pick_indices(draw(P, TAG_IDX, g, i, 0), N, i, r0, r1, r2);
@@ -183,20 +186,17 @@ __global__ void __launch_bounds__(64) k_pexp_trial(const RunDev* __restrict__ ru
 }
 
 // ---- best so far (Tables 3-5: best value, best gen) ------------------------
-// One block per run: argmin of the fitness (lowest index on ties); a strictly
-// better value than the best so far records the generation.  The block then
-// advances the run's generation count.
+
+// argmin over n values (lowest index on ties) with one 256-thread block.
 template <typename T>
-__device__ void best_of_run(const RunDev& P, bool init) {
-  __shared__ T sf[256];
+__device__ GenMin block_argmin(const T* v, int64_t n) {
+  __shared__ double sf[256];
   __shared__ int64_t si[256];
-  const int64_t N = P.N;
-  const T* fit = static_cast<const T*>(P.fit);
-  T bf = Math<T>::inf();
-  int64_t bi = N;
-  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-    const T f = fit[i];
-    if (bi == N || f < bf) {  // strict: the lowest index keeps a tie
+  double bf = __builtin_huge_val();
+  int64_t bi = n;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double f = static_cast<double>(v[i]);
+    if (bi == n || f < bf) {  // strict: the lowest index keeps a tie
       bf = f;
       bi = i;
     }
@@ -206,52 +206,80 @@ __device__ void best_of_run(const RunDev& P, bool init) {
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
-      const T f2 = sf[threadIdx.x + s];
-      const int64_t i2 = si[threadIdx.x + s];
-      const T f1 = sf[threadIdx.x];
-      const int64_t i1 = si[threadIdx.x];
-      if (i2 < N && (i1 >= N || f2 < f1 || (f2 == f1 && i2 < i1))) {
+      const double f2 = sf[threadIdx.x + s], f1 = sf[threadIdx.x];
+      const int64_t i2 = si[threadIdx.x + s], i1 = si[threadIdx.x];
+      if (i2 < n && (i1 >= n || f2 < f1 || (f2 == f1 && i2 < i1))) {
         sf[threadIdx.x] = f2;
         si[threadIdx.x] = i2;
       }
     }
     __syncthreads();
   }
+  GenMin r{sf[0], si[0] < n ? si[0] : 0};
+  __syncthreads();
+  return r;
+}
+
+// Generation 0: the best of the initial population (one block per run).
+__global__ void __launch_bounds__(256) k_best_init(const RunDev* __restrict__ runs) {
+  const RunDev& P = runs[blockIdx.x];
+  const GenMin m = P.dtype == 0 ? block_argmin(static_cast<const double*>(P.fit), P.N)
+                                : block_argmin(static_cast<const float*>(P.fit), P.N);
   if (threadIdx.x == 0) {
     BestState* B = P.best;
-    const double fm = static_cast<double>(sf[0]);
-    const int64_t im = si[0] < N ? si[0] : 0;
-    if (init) {
-      B->f = fm;
-      B->idx = im;
-      B->gen = 0;
-      B->g = 0;
-    } else {
-      const uint32_t g = B->g + 1;
-      if (fm < B->f) {
-        B->f = fm;
-        B->idx = im;
-        B->gen = g;
-      }
-      B->g = g;
-    }
+    B->f = m.f;
+    B->idx = m.idx;
+    B->gen = run_gen(P, 0);
+    B->g = run_gen(P, 0);
   }
 }
 
-__global__ void __launch_bounds__(256) k_best(const RunDev* __restrict__ runs, int init) {
-  const RunDev& P = runs[blockIdx.x];
-  if (P.dtype == 0) best_of_run<double>(P, init != 0);
-  else best_of_run<float>(P, init != 0);
+// Deferred update, pass 1: the minimum over the rows each generation
+// replaced (block (k, run) handles generation gfirst + k of that run).
+__global__ void __launch_bounds__(256) k_best_gen_min(const RunDev* __restrict__ runs,
+                                                      uint32_t gfirst) {
+  const RunDev& P = runs[blockIdx.y];
+  const uint32_t gnew = gfirst + blockIdx.x;
+  const int64_t off = static_cast<int64_t>(gnew % kHist) * P.N;
+  const GenMin m = P.dtype == 0 ? block_argmin(static_cast<const double*>(P.hist) + off, P.N)
+                                : block_argmin(static_cast<const float*>(P.hist) + off, P.N);
+  if (threadIdx.x == 0) P.mins[gnew % kHist] = m;
+}
+
+// Pass 2: walk the generations in order; a strictly lower minimum than the
+// best so far records that generation.  Between improvements every row keeps
+// f_i >= best, so the minimum over the replaced rows decides.
+__global__ void k_best_scan(const RunDev* __restrict__ runs, int n_runs, uint32_t gfirst,
+                            int count) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_runs) return;
+  const RunDev& P = runs[r];
+  BestState* B = P.best;
+  double bf = B->f;
+  int64_t bi = B->idx, bg = B->gen;
+  for (int k = 0; k < count; ++k) {
+    const uint32_t gnew = gfirst + k;
+    const GenMin m = P.mins[gnew % kHist];
+    if (m.f < bf) {
+      bf = m.f;
+      bi = m.idx;
+      bg = run_gen(P, gnew);
+    }
+  }
+  B->f = bf;
+  B->idx = bi;
+  B->gen = bg;
+  B->g = run_gen(P, gfirst + count - 1);
 }
 
 // FP64 fitness of the best row, recomputed from the stored vector.
 template <typename T>
 __global__ void __launch_bounds__(256) k_best_fp64(const RunDev* __restrict__ runs, int32_t run,
-                                                   double* __restrict__ out) {
+                                                   uint32_t gcur, double* __restrict__ out) {
   const RunDev& P = runs[run];
   const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
   const int64_t i = P.best->idx;
-  const uint8_t* cur = P.flags + (P.best->g & 1u) * static_cast<int64_t>(N);
+  const uint8_t* cur = P.flags + (run_gen(P, gcur) & 1u) * static_cast<int64_t>(N);
   const T* x = static_cast<const T*>(P.X[cur[i]]) + i * P.ld;
   const T* o = static_cast<const T*>(P.o);
   __shared__ double red[4];
@@ -288,10 +316,11 @@ __global__ void __launch_bounds__(256) k_best_fp64(const RunDev* __restrict__ ru
 // Move every row into buffer 0 (rows whose current copy is in buffer 1 are
 // copied back) and clear the current flags, so buffer 0 is the population.
 template <typename T>
-__global__ void __launch_bounds__(256) k_normalize(const RunDev* __restrict__ runs, int32_t run) {
+__global__ void __launch_bounds__(256) k_normalize(const RunDev* __restrict__ runs, int32_t run,
+                                                   uint32_t gcur) {
   const RunDev& P = runs[run];
   const int64_t N = P.N, ld = P.ld;
-  const uint32_t g = P.best->g;
+  const uint32_t g = run_gen(P, gcur);
   uint8_t* cur = P.flags + (g & 1u) * N;
   const int64_t i = blockIdx.x;
   if (cur[i] == 0) return;
@@ -344,33 +373,46 @@ hipError_t launch_eval_rows(const RunDev& h, const void* X, int64_t rows, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_eval_select(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
-  if (h.dtype == 0) hipLaunchKernelGGL(k_eval_select<double>, dim3(h.N), dim3(256), 0, s, runs, run);
-  else hipLaunchKernelGGL(k_eval_select<float>, dim3(h.N), dim3(256), 0, s, runs, run);
+hipError_t launch_eval_select(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+                              hipStream_t s) {
+  if (h.dtype == 0) hipLaunchKernelGGL(k_eval_select<double>, dim3(h.N), dim3(256), 0, s, runs, run, gnew);
+  else hipLaunchKernelGGL(k_eval_select<float>, dim3(h.N), dim3(256), 0, s, runs, run, gnew);
   return hipGetLastError();
 }
 
-hipError_t launch_pexp_trial(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
-  if (h.dtype == 0) hipLaunchKernelGGL(k_pexp_trial<double>, dim3(nblk(h.N, 64)), dim3(64), 0, s, runs, run);
-  else hipLaunchKernelGGL(k_pexp_trial<float>, dim3(nblk(h.N, 64)), dim3(64), 0, s, runs, run);
+hipError_t launch_pexp_trial(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+                             hipStream_t s) {
+  if (h.dtype == 0) hipLaunchKernelGGL(k_pexp_trial<double>, dim3(nblk(h.N, 64)), dim3(64), 0, s, runs, run, gnew);
+  else hipLaunchKernelGGL(k_pexp_trial<float>, dim3(nblk(h.N, 64)), dim3(64), 0, s, runs, run, gnew);
   return hipGetLastError();
 }
 
-hipError_t launch_best(const RunDev* runs, int n_runs, bool init, hipStream_t s) {
-  hipLaunchKernelGGL(k_best, dim3(n_runs), dim3(256), 0, s, runs, init ? 1 : 0);
+hipError_t launch_best_init(const RunDev* runs, int n_runs, hipStream_t s) {
+  hipLaunchKernelGGL(k_best_init, dim3(n_runs), dim3(256), 0, s, runs);
   return hipGetLastError();
 }
 
-hipError_t launch_best_fp64(const RunDev* runs, const RunDev& h, int run, double* out,
+hipError_t launch_best_flush(const RunDev* runs, int n_runs, int64_t max_rows, uint32_t gfirst,
+                             int count, hipStream_t s) {
+  (void)max_rows;
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_best_gen_min, dim3(count, n_runs), dim3(256), 0, s, runs, gfirst);
+  hipLaunchKernelGGL(k_best_scan, dim3(nblk(n_runs, 256)), dim3(256), 0, s, runs, n_runs, gfirst,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_fp64(const RunDev* runs, const RunDev& h, int run, uint32_t gcur,
+                            double* out, hipStream_t s) {
+  if (h.dtype == 0) hipLaunchKernelGGL(k_best_fp64<double>, dim3(1), dim3(256), 0, s, runs, run, gcur, out);
+  else hipLaunchKernelGGL(k_best_fp64<float>, dim3(1), dim3(256), 0, s, runs, run, gcur, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(const RunDev* runs, const RunDev& h, int run, uint32_t gcur,
                             hipStream_t s) {
-  if (h.dtype == 0) hipLaunchKernelGGL(k_best_fp64<double>, dim3(1), dim3(256), 0, s, runs, run, out);
-  else hipLaunchKernelGGL(k_best_fp64<float>, dim3(1), dim3(256), 0, s, runs, run, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_normalize(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
-  if (h.dtype == 0) hipLaunchKernelGGL(k_normalize<double>, dim3(h.N), dim3(256), 0, s, runs, run);
-  else hipLaunchKernelGGL(k_normalize<float>, dim3(h.N), dim3(256), 0, s, runs, run);
+  if (h.dtype == 0) hipLaunchKernelGGL(k_normalize<double>, dim3(h.N), dim3(256), 0, s, runs, run, gcur);
+  else hipLaunchKernelGGL(k_normalize<float>, dim3(h.N), dim3(256), 0, s, runs, run, gcur);
   return hipGetLastError();
 }
 

@@ -59,11 +59,13 @@ __device__ __forceinline__ void split3(float v, __bf16& a, __bf16& b, __bf16& c)
 //   src 0: trials of the coming generation (non-current buffer of each row)
 //   src 1: current population
 //   src 2: staging rows (caller data for de_evaluate)
+//   gh: handle generation (the one being computed for src 0, the current one
+//   for src 1)
 template <typename T>
-__device__ __forceinline__ const T* a_row(const RunDev& P, int src, int64_t i) {
+__device__ __forceinline__ const T* a_row(const RunDev& P, int src, uint32_t gh, int64_t i) {
   if (src == 2) return static_cast<const T*>(P.stage) + i * P.ld;
   const uint32_t N = static_cast<uint32_t>(P.N);
-  const uint32_t g = P.best->g + (src == 0 ? 1u : 0u);
+  const uint32_t g = run_gen(P, gh);
   const uint8_t* cur = P.flags + ((src == 0 ? g - 1 : g) & 1u) * static_cast<int64_t>(N);
   const uint32_t b = cur[i] ^ (src == 0 ? 1u : 0u);
   return static_cast<const T*>(P.X[b]) + i * P.ld;
@@ -71,7 +73,7 @@ __device__ __forceinline__ const T* a_row(const RunDev& P, int src, int64_t i) {
 
 template <int MODE>
 __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ runs, int32_t run,
-                                                 int src, int64_t rows) {
+                                                 int src, uint32_t gh, int64_t rows) {
   using C = MM<MODE>;
   using T = typename C::T;
   using LT = typename C::L;
@@ -101,7 +103,7 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   constexpr int A_SEG = KT / A_TPR;          // values per thread
   const int a_r = tid / A_TPR, a_k = (tid % A_TPR) * A_SEG;
   const int64_t ai = min(row0 + a_r, rows - 1);
-  const T* arow = a_row<T>(Pr, src, ai);
+  const T* arow = a_row<T>(Pr, src, gh, ai);
   const T* o = static_cast<const T*>(Pr.o);
   // B-load assignment, same shape over the BN rows of M.
   constexpr int B_TPR = 256 / BN;
@@ -253,12 +255,12 @@ __device__ __forceinline__ T row_total(const RunDev& P, int64_t i, int ntn) {
 
 // Greedy selection on the trials of generation g (Alg 2 lines 11-14).
 template <typename T>
-__global__ void k_rot_select(const RunDev* __restrict__ runs, int32_t run, int ntn) {
+__global__ void k_rot_select(const RunDev* __restrict__ runs, int32_t run, int ntn, uint32_t gnew) {
   const RunDev& P = runs[run];
   const uint32_t N = static_cast<uint32_t>(P.N);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const uint32_t g = P.best->g + 1;
+  const uint32_t g = run_gen(P, gnew);
   const uint8_t* cur = P.flags + ((g - 1) & 1u) * static_cast<int64_t>(N);
   uint8_t* nxt = P.flags + (g & 1u) * static_cast<int64_t>(N);
   const uint32_t ci = cur[i];
@@ -267,6 +269,7 @@ __global__ void k_rot_select(const RunDev* __restrict__ runs, int32_t run, int n
   const bool win = fu < fit[i];
   nxt[i] = static_cast<uint8_t>(win ? ci ^ 1u : ci);
   if (win) fit[i] = fu;
+  static_cast<T*>(P.hist)[static_cast<int64_t>(gnew % kHist) * N + i] = win ? fu : Math<T>::inf();
   if (P.tr_idx) P.tr_idx[6 * static_cast<int64_t>(i) + 5] = win ? 1 : 0;
   if (P.tr_ftrial) static_cast<T*>(P.tr_ftrial)[i] = fu;
 }
@@ -347,34 +350,35 @@ hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s) {
   return hipGetLastError();
 }
 
-static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, int64_t rows,
-                       hipStream_t s) {
+static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, uint32_t gh,
+                       int64_t rows, hipStream_t s) {
   const int bm = tile_m_of(h.mm), bn = tile_n_of(h.mm);
   const int64_t blocks = ((rows + bm - 1) / bm) * ((h.D + bn - 1) / bn);
   switch (h.mm) {
-    case MM_FP64: hipLaunchKernelGGL(k_rot_gemm<MM_FP64>, dim3(blocks), dim3(256), 0, s, runs, run, src, rows); break;
-    case MM_FP32: hipLaunchKernelGGL(k_rot_gemm<MM_FP32>, dim3(blocks), dim3(256), 0, s, runs, run, src, rows); break;
-    case MM_BF16X3: hipLaunchKernelGGL(k_rot_gemm<MM_BF16X3>, dim3(blocks), dim3(256), 0, s, runs, run, src, rows); break;
-    case MM_BF16X6: hipLaunchKernelGGL(k_rot_gemm<MM_BF16X6>, dim3(blocks), dim3(256), 0, s, runs, run, src, rows); break;
+    case MM_FP64: hipLaunchKernelGGL(k_rot_gemm<MM_FP64>, dim3(blocks), dim3(256), 0, s, runs, run, src, gh, rows); break;
+    case MM_FP32: hipLaunchKernelGGL(k_rot_gemm<MM_FP32>, dim3(blocks), dim3(256), 0, s, runs, run, src, gh, rows); break;
+    case MM_BF16X3: hipLaunchKernelGGL(k_rot_gemm<MM_BF16X3>, dim3(blocks), dim3(256), 0, s, runs, run, src, gh, rows); break;
+    case MM_BF16X6: hipLaunchKernelGGL(k_rot_gemm<MM_BF16X6>, dim3(blocks), dim3(256), 0, s, runs, run, src, gh, rows); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, bool trials,
+hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
                               hipStream_t s) {
-  return gemm(runs, h, run, trials ? 0 : 1, h.N, s);
+  return gemm(runs, h, run, 0, gnew, h.N, s);
 }
 
-hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
+hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+                             hipStream_t s) {
   const int ntn = static_cast<int>((h.D + tile_n_of(h.mm) - 1) / tile_n_of(h.mm));
-  if (h.dtype == 0) hipLaunchKernelGGL(k_rot_select<double>, dim3(nb(h.N, 256)), dim3(256), 0, s, runs, run, ntn);
-  else hipLaunchKernelGGL(k_rot_select<float>, dim3(nb(h.N, 256)), dim3(256), 0, s, runs, run, ntn);
+  if (h.dtype == 0) hipLaunchKernelGGL(k_rot_select<double>, dim3(nb(h.N, 256)), dim3(256), 0, s, runs, run, ntn, gnew);
+  else hipLaunchKernelGGL(k_rot_select<float>, dim3(nb(h.N, 256)), dim3(256), 0, s, runs, run, ntn, gnew);
   return hipGetLastError();
 }
 
 hipError_t launch_rot_init_fit(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
-  hipError_t e = gemm(runs, h, run, 1, h.N, s);
+  hipError_t e = gemm(runs, h, run, 1, 0, h.N, s);
   if (e != hipSuccess) return e;
   const int ntn = static_cast<int>((h.D + tile_n_of(h.mm) - 1) / tile_n_of(h.mm));
   if (h.dtype == 0)
@@ -401,7 +405,7 @@ hipError_t launch_rot_eval_rows(const RunDev* runs, const RunDev& h, int run, co
     else
       hipLaunchKernelGGL(k_rot_stage<float>, dim3(nb(n * h.ld, 256)), dim3(256), 0, s,
                          static_cast<float*>(h.stage), h.ld, reinterpret_cast<const float*>(src), h.D, n);
-    hipError_t e = gemm(runs, h, run, 2, n, s);
+    hipError_t e = gemm(runs, h, run, 2, 0, n, s);
     if (e != hipSuccess) return e;
     if (h.dtype == 0)
       hipLaunchKernelGGL(k_rot_store<double>, dim3(nb(n, 256)), dim3(256), 0, s, runs, run, ntn, n,
