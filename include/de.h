@@ -158,10 +158,13 @@ de_status de_set_state(de_handle* h, int32_t run, const void* pop_host, const vo
 de_status de_trace(de_handle* h, int32_t run, int64_t* idx, uint8_t* mask, void* trial,
                    void* ftrial);
 
-/* Kernel timing for measurement: while enabled, de_generation brackets every
- * launch of the generation's main kernel with HIP events on the launch stream.
- * de_profile_read syncs, adds up the elapsed times recorded since enabling
- * and returns (total ms of the main kernel, number of its launches). */
+/* Kernel timing for measurement: while enabled, de_generation records HIP
+ * events on the launch stream around the generation's main kernel: around
+ * each launch when a generation takes several kernels (rotated function, or
+ * the job-per-individual exponential crossover), else around the whole run
+ * of back-to-back generation launches of the call.  de_profile_read syncs
+ * and returns the elapsed milliseconds recorded since enabling and the number
+ * of main-kernel launches they cover. */
 de_status de_profile(de_handle* h, int32_t enable);
 de_status de_profile_read(de_handle* h, double* main_ms, int64_t* main_launches);
 

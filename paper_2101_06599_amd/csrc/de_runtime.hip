@@ -37,6 +37,8 @@ struct de_handle {
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
+  std::vector<int64_t> ev_launches;  // main-kernel launches between event pairs
+  bool single_kernel = false;        // every generation is one kernel launch
 };
 
 namespace {
@@ -194,11 +196,12 @@ int pick_tpr(const de_run_desc& d, bool batched) {
   if (batched) return 64;
   if (const char* e = std::getenv("DE_TPR")) {
     int v = std::atoi(e);
-    if (v == 64 || v == 256 || v == 1024) return v;
+    if (v == 64 || v == 256 || v == 512 || v == 1024) return v;
   }
   const int64_t nchunk = (d.D + 3) / 4;
   if (nchunk <= 64 * 4) return 64;
   if (nchunk <= 256 * 4) return 256;
+  if (nchunk <= 512 * 5) return 512;
   return 1024;
 }
 
@@ -215,6 +218,10 @@ hipEvent_t next_event(de_handle* h) {
   return h->ev_pool[h->ev_used++];
 }
 
+void add_pair_count(de_handle* h, int64_t n) {
+  if (h->ev_used % 2 == 0 && h->ev_used >= 2) h->ev_launches.push_back(n);
+}
+
 // Best-so-far over the generations run since the last update.
 de_status flush_best(de_handle* h, hipStream_t s) {
   if (h->pending == 0) return DE_OK;
@@ -227,10 +234,13 @@ de_status flush_best(de_handle* h, hipStream_t s) {
 // The launches of one generation of one run (single-run handles) or of all
 // runs (batched); `mark` brackets the dominant kernel with events if enabled.
 de_status one_generation(de_handle* h, hipStream_t s) {
+  // per-launch event pairs only where a generation has several kernels; a
+  // one-kernel generation is timed as a span of launches in de_generation
   auto mark = [&]() {
-    if (!h->prof) return;
+    if (!h->prof || h->single_kernel) return;
     hipEvent_t e = next_event(h);
     if (e) (void)hipEventRecord(e, s);
+    add_pair_count(h, 1);
   };
   const uint32_t gnew = h->done + 1;
   if (h->batched) {
@@ -363,6 +373,10 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
     T[d.D + 1] = 0;
     h->tpr[r] = pick_tpr(d, h->batched);
   }
+  h->single_kernel = true;
+  for (int r = 0; r < n_runs; ++r)
+    if (runs[r].fn == DE_FN_ELLIPSOID_ROT || (runs[r].xo == DE_XO_EXP && runs[r].exp_impl == DE_EXP_JOB))
+      h->single_kernel = false;
   if (h->batched) {
     for (int r = 0; r < n_runs; ++r)
       for (int64_t i = 0; i < runs[r].N; ++i)
@@ -414,9 +428,19 @@ de_status de_generation(de_handle* h, int32_t n_gens, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (static_cast<uint64_t>(h->done) + static_cast<uint64_t>(n_gens) >= 0xFFFFFFF0ull)
     return fail(h, DE_E_STATE, "generation counter would overflow");
+  const bool span = h->prof && h->single_kernel && n_gens > 0;
+  if (span) {
+    hipEvent_t e = next_event(h);
+    if (e) (void)hipEventRecord(e, s);
+  }
   for (int32_t k = 0; k < n_gens; ++k) {
     de_status st = one_generation(h, s);
     if (st != DE_OK) return st;
+  }
+  if (span) {
+    hipEvent_t e = next_event(h);
+    if (e) (void)hipEventRecord(e, s);
+    add_pair_count(h, n_gens);
   }
   return flush_best(h, s);
 }
@@ -551,6 +575,7 @@ de_status de_profile(de_handle* h, int32_t enable) {
   if (!h) return fail(nullptr, DE_E_INVALID, "NULL handle");
   h->prof = enable != 0;
   h->ev_used = 0;
+  h->ev_launches.clear();
   return DE_OK;
 }
 
@@ -563,7 +588,7 @@ de_status de_profile_read(de_handle* h, double* main_ms, int64_t* main_launches)
     float ms = 0.0f;
     HIPCHECK(h, hipEventElapsedTime(&ms, h->ev_pool[k], h->ev_pool[k + 1]));
     total += ms;
-    ++n;
+    n += k / 2 < h->ev_launches.size() ? h->ev_launches[k / 2] : 1;
   }
   if (main_ms) *main_ms = total;
   if (main_launches) *main_launches = n;

@@ -143,6 +143,12 @@ template <int TPR> struct Shape {
   static constexpr int BS = TPR >= 256 ? TPR : 256;  // threads per block
   static constexpr int RPB = BS / TPR;               // rows per block
   static constexpr int NW = TPR / 64;                // wavefronts per row
+  // wide rows: ask for 8 waves per SIMD (<= 64 VGPRs) so that two rows'
+  // blocks share a CU; narrow rows keep the compiler's choice
+  static constexpr int MINW = 1;
+  // chunks of 4 elements held in registers per thread: D <= 16 * TPR (20 * 512
+  // for 512-wide rows) stays in registers between evaluation and write-back
+  static constexpr int MAXIT = TPR == 512 ? 5 : 4;
 };
 
 // FN: a fixed function, FN_ANY (taken from the run record) or FN_NONE (build
@@ -150,7 +156,7 @@ template <int TPR> struct Shape {
 // XO: a fixed crossover or XO_ANY.  BATCH: rows come from a row map that
 // spans several runs.
 template <typename T, int FN, int XO, int TPR, int MAXIT, bool BATCH>
-__global__ void __launch_bounds__(Shape<TPR>::BS)
+__global__ void __launch_bounds__(Shape<TPR>::BS, Shape<TPR>::MINW)
 k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* __restrict__ rowmap,
              int64_t rows, uint32_t gnew) {
   using S = Shape<TPR>;
@@ -197,8 +203,16 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
 
   const uint8_t* cur = P.flags + ((R.g - 1) & 1u) * static_cast<int64_t>(N);
   uint8_t* nxt = P.flags + (R.g & 1u) * static_cast<int64_t>(N);
-  const uint32_t ci = cur[i];
-  const uint32_t c0 = cur[r0], c1 = cur[r1], c2 = cur[r2];
+  // wave-uniform by construction; keep them (and the row pointers) scalar
+  r0 = __builtin_amdgcn_readfirstlane(r0);
+  r1 = __builtin_amdgcn_readfirstlane(r1);
+  r2 = __builtin_amdgcn_readfirstlane(r2);
+  R.jr = __builtin_amdgcn_readfirstlane(R.jr);
+  R.L = __builtin_amdgcn_readfirstlane(R.L);
+  const uint32_t ci = __builtin_amdgcn_readfirstlane(cur[i]);
+  const uint32_t c0 = __builtin_amdgcn_readfirstlane(cur[r0]);
+  const uint32_t c1 = __builtin_amdgcn_readfirstlane(cur[r1]);
+  const uint32_t c2 = __builtin_amdgcn_readfirstlane(cur[r2]);
   R.xi = static_cast<const T*>(P.X[ci]) + static_cast<int64_t>(i) * ld;
   R.x0 = static_cast<const T*>(P.X[c0]) + static_cast<int64_t>(r0) * ld;
   R.x1 = static_cast<const T*>(P.X[c1]) + static_cast<int64_t>(r1) * ld;
@@ -345,10 +359,10 @@ static hipError_t go(const GenLaunch& L, bool batched) {
   const int64_t blocks = (L.rows + S::RPB - 1) / S::RPB;
   if (blocks <= 0) return hipSuccess;
   if (batched)
-    hipLaunchKernelGGL((k_generation<T, FN, XO, TPR, 4, true>), dim3(blocks), dim3(S::BS), 0, L.s,
+    hipLaunchKernelGGL((k_generation<T, FN, XO, TPR, S::MAXIT, true>), dim3(blocks), dim3(S::BS), 0, L.s,
                        L.runs, L.run, L.rowmap, L.rows, L.gnew);
   else
-    hipLaunchKernelGGL((k_generation<T, FN, XO, TPR, 4, false>), dim3(blocks), dim3(S::BS), 0, L.s,
+    hipLaunchKernelGGL((k_generation<T, FN, XO, TPR, S::MAXIT, false>), dim3(blocks), dim3(S::BS), 0, L.s,
                        L.runs, L.run, L.rowmap, L.rows, L.gnew);
   return hipGetLastError();
 }
@@ -358,6 +372,7 @@ static hipError_t go_tpr(const GenLaunch& L, bool batched) {
   switch (L.tpr) {
     case 64: return go<T, FN, XO, 64>(L, batched);
     case 256: return go<T, FN, XO, 256>(L, batched);
+    case 512: return go<T, FN, XO, 512>(L, batched);
     case 1024: return go<T, FN, XO, 1024>(L, batched);
     default: return hipErrorInvalidValue;
   }
