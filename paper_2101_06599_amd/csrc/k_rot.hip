@@ -71,6 +71,19 @@ __device__ __forceinline__ const T* a_row(const RunDev& P, int src, uint32_t gh,
   return static_cast<const T*>(P.X[b]) + i * P.ld;
 }
 
+// 16-byte vector moves of N elements of type V (N * sizeof(V) a multiple of 16).
+template <typename V, int N>
+__device__ __forceinline__ void copy16(V* __restrict__ dst, const V* __restrict__ src) {
+  static_assert((N * sizeof(V)) % 16 == 0, "whole 16-byte vectors");
+#pragma unroll
+  for (int q = 0; q < static_cast<int>(N * sizeof(V) / 16); ++q)
+    reinterpret_cast<uint4*>(dst)[q] = reinterpret_cast<const uint4*>(src)[q];
+}
+
+// The product for one 128x128 (FP64: 64x64) tile of Z.  The next K slice is
+// fetched into registers while the matrix cores work on the current one from
+// LDS; the slice is then split (bf16 modes) and written into the other LDS
+// buffer, so one barrier per K step separates the two.
 template <int MODE>
 __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ runs, int32_t run,
                                                  int src, uint32_t gh, int64_t rows) {
@@ -79,8 +92,12 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   using LT = typename C::L;
   constexpr int BM = C::BM, BN = C::BN, KT = C::KT, P = C::P, LDK = KT + C::PAD;
   constexpr int WM = BM / 32, WN = BN / 32;  // 16x16 subtiles per wave (2x2 waves)
-  __shared__ __attribute__((aligned(16))) LT As[P][BM][LDK];
-  __shared__ __attribute__((aligned(16))) LT Bs[P][BN][LDK];
+  // FP32/FP64 slices are small: two LDS buffers, one barrier per K step.  The
+  // split-bf16 slices are 2-3x larger: one buffer (two barriers per step) so
+  // that two blocks fit on a CU.
+  constexpr int NBUF = P == 1 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) LT As[NBUF][P][BM][LDK];
+  __shared__ __attribute__((aligned(16))) LT Bs[NBUF][P][BN][LDK];
   __shared__ T red[2][BM];
 
   const RunDev& Pr = runs[run];
@@ -98,18 +115,45 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave / 2, wn = wave % 2;
 
-  // A-load assignment: each thread covers one row segment of the K tile.
-  constexpr int A_TPR = 256 / BM;            // threads per A row
-  constexpr int A_SEG = KT / A_TPR;          // values per thread
+  // Global -> LDS assignment: each thread moves one row segment of the A and
+  // of the B slice (A_SEG, B_SEG contiguous values; 32 bytes or more).
+  constexpr int A_TPR = 256 / BM, A_SEG = KT / A_TPR;
+  constexpr int B_TPR = 256 / BN, B_SEG = KT / B_TPR;
   const int a_r = tid / A_TPR, a_k = (tid % A_TPR) * A_SEG;
-  const int64_t ai = min(row0 + a_r, rows - 1);
-  const T* arow = a_row<T>(Pr, src, gh, ai);
-  const T* o = static_cast<const T*>(Pr.o);
-  // B-load assignment, same shape over the BN rows of M.
-  constexpr int B_TPR = 256 / BN;
-  constexpr int B_SEG = KT / B_TPR;
   const int b_r = tid / B_TPR, b_k = (tid % B_TPR) * B_SEG;
-  const int64_t bn = col0 + b_r;  // rows of M pieces are padded to a multiple of 128
+  const int64_t ai = min(row0 + a_r, rows - 1);
+  const T* arow = a_row<T>(Pr, src, gh, ai) + a_k;
+  const T* orow = static_cast<const T*>(Pr.o) + a_k;
+  const LT* brow[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p)  // rows of M pieces are padded to a multiple of 128
+    brow[p] = static_cast<const LT*>(Pr.B[p]) + (col0 + b_r) * ldk + b_k;
+
+  __attribute__((aligned(16))) T ra[A_SEG], ro[A_SEG];
+  __attribute__((aligned(16))) LT rb[P][B_SEG];
+  auto fetch = [&](int64_t k0) {
+    copy16<T, A_SEG>(ra, arow + k0);
+    copy16<T, A_SEG>(ro, orow + k0);  // padding columns hold zeros on both sides
+#pragma unroll
+    for (int p = 0; p < P; ++p) copy16<LT, B_SEG>(rb[p], brow[p] + k0);
+  };
+  auto stash = [&](int buf) {
+    if constexpr (P == 1) {
+      __attribute__((aligned(16))) T a[A_SEG];
+#pragma unroll
+      for (int e = 0; e < A_SEG; ++e) a[e] = ra[e] - ro[e];
+      copy16<T, A_SEG>(&As[buf][0][a_r][a_k], a);
+    } else {
+      __attribute__((aligned(16))) __bf16 h[A_SEG], m[A_SEG], l[A_SEG];
+#pragma unroll
+      for (int e = 0; e < A_SEG; ++e) split3(ra[e] - ro[e], h[e], m[e], l[e]);
+      copy16<__bf16, A_SEG>(&As[buf][0][a_r][a_k], h);
+      copy16<__bf16, A_SEG>(&As[buf][1][a_r][a_k], m);
+      if constexpr (P == 3) copy16<__bf16, A_SEG>(&As[buf][2][a_r][a_k], l);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) copy16<LT, B_SEG>(&Bs[buf][p][b_r][b_k], rb[p]);
+  };
 
   using Acc = typename std::conditional<MODE == MM_FP64, f64x4, f32x4>::type;
   Acc acc[WM][WN];
@@ -121,39 +165,20 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
       for (int r = 0; r < 4; ++r) acc[m][n][r] = 0;
 
   const int nk = static_cast<int>((D + KT - 1) / KT);
+  fetch(0);
+  stash(0);
+  __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    const int64_t k0 = static_cast<int64_t>(kt) * KT;
-    // ---- global -> LDS ----
-#pragma unroll
-    for (int e = 0; e < A_SEG; ++e) {
-      const int64_t k = k0 + a_k + e;
-      const T a = arow[k] - o[k];  // padding columns hold zeros on both sides
-      if constexpr (P == 1) {
-        As[0][a_r][a_k + e] = a;
-      } else {
-        __bf16 h, m, l;
-        split3(a, h, m, l);
-        As[0][a_r][a_k + e] = h;
-        As[1][a_r][a_k + e] = m;
-        if constexpr (P == 3) As[2][a_r][a_k + e] = l;
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const LT* brow = static_cast<const LT*>(Pr.B[p]) + bn * ldk + k0 + b_k;
-#pragma unroll
-      for (int e = 0; e < B_SEG; ++e) Bs[p][b_r][b_k + e] = brow[e];
-    }
-    __syncthreads();
-    // ---- LDS -> matrix cores ----
+    const int buf = NBUF == 2 ? (kt & 1) : 0;
+    if (kt + 1 < nk) fetch(static_cast<int64_t>(kt + 1) * KT);
     if constexpr (P == 1) {
 #pragma unroll
       for (int s = 0; s < KT / 4; ++s) {
         T af[WM], bf[WN];
 #pragma unroll
-        for (int m = 0; m < WM; ++m) af[m] = As[0][wm * (BM / 2) + m * 16 + lane % 16][4 * s + lane / 16];
+        for (int m = 0; m < WM; ++m) af[m] = As[buf][0][wm * (BM / 2) + m * 16 + lane % 16][4 * s + lane / 16];
 #pragma unroll
-        for (int n = 0; n < WN; ++n) bf[n] = Bs[0][wn * (BN / 2) + n * 16 + lane % 16][4 * s + lane / 16];
+        for (int n = 0; n < WN; ++n) bf[n] = Bs[buf][0][wn * (BN / 2) + n * 16 + lane % 16][4 * s + lane / 16];
 #pragma unroll
         for (int m = 0; m < WM; ++m)
 #pragma unroll
@@ -171,26 +196,31 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
 #pragma unroll
         for (int m = 0; m < WM; ++m)
           af[p][m] = *reinterpret_cast<const bf16x8*>(
-              &As[p][wm * (BM / 2) + m * 16 + lane % 16][8 * (lane / 16)]);
+              &As[buf][p][wm * (BM / 2) + m * 16 + lane % 16][8 * (lane / 16)]);
 #pragma unroll
         for (int n = 0; n < WN; ++n)
           bfr[p][n] = *reinterpret_cast<const bf16x8*>(
-              &Bs[p][wn * (BN / 2) + n * 16 + lane % 16][8 * (lane / 16)]);
+              &Bs[buf][p][wn * (BN / 2) + n * 16 + lane % 16][8 * (lane / 16)]);
       }
+      // piece products, smallest first; the product loop is outermost so that
+      // consecutive matrix-core ops use different accumulators
+      constexpr int NPR = P == 3 ? 6 : 3;
+      constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+      constexpr int P0 = P == 3 ? 0 : 3;
 #pragma unroll
-      for (int m = 0; m < WM; ++m)
+      for (int q = 0; q < NPR; ++q)
 #pragma unroll
-        for (int n = 0; n < WN; ++n) {
-          // smallest products first
-          if constexpr (P == 3) {
-            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][m], bfr[0][n], acc[m][n], 0, 0, 0);
-            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][m], bfr[1][n], acc[m][n], 0, 0, 0);
-            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][m], bfr[2][n], acc[m][n], 0, 0, 0);
-          }
-          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][m], bfr[0][n], acc[m][n], 0, 0, 0);
-          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][m], bfr[1][n], acc[m][n], 0, 0, 0);
-          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][m], bfr[0][n], acc[m][n], 0, 0, 0);
-        }
+        for (int m = 0; m < WM; ++m)
+#pragma unroll
+          for (int n = 0; n < WN; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PA[P0 + q]][m], bfr[PB[P0 + q]][n],
+                                                                acc[m][n], 0, 0, 0);
+    }
+    if constexpr (NBUF == 1) {
+      __syncthreads();  // every wave is done with the slice before it is replaced
+      if (kt + 1 < nk) stash(0);
+    } else {
+      if (kt + 1 < nk) stash(buf ^ 1);
     }
     __syncthreads();
   }
