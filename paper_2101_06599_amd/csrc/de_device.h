@@ -67,17 +67,24 @@ __device__ __forceinline__ void pick_indices(uint4 b, uint32_t N, uint32_t i, ui
 }
 
 // NEC run length from word w: the number of k in [1, D] with w < T[k], where
-// T[k] counts the words whose uniform lies below CR^(k-1).  A logarithm gives
-// the starting guess; the table settles it exactly.
+// T[k] is the number of words whose uniform (w + 1/2) 2^-32 lies below
+// CR^(k-1) (the power as a running FP64 product).  T decreases in k, so the k
+// that pass form a prefix: each lane of the wavefront tests one k, 64 at a
+// time (one coalesced load of the table), and the run length is the count.
+// Must be called by the whole wavefront with the same w.
 __device__ __forceinline__ uint32_t nec_length(const RunDev& P, uint32_t w) {
   const uint32_t D = static_cast<uint32_t>(P.D);
   if (P.inv_ln_cr == 0.0) return P.CR >= 1.0 ? D : 1u;
-  const float U = (static_cast<float>(w) + 0.5f) * 0x1p-32f;
-  float e = ceilf(__logf(U) * static_cast<float>(P.inv_ln_cr));
-  uint32_t L = e < 1.0f ? 1u : (e >= static_cast<float>(D) ? D : static_cast<uint32_t>(e));
+  const uint32_t lane = __lane_id();
   const uint64_t ww = w;
-  while (L > 1 && !(ww < P.T[L])) --L;
-  while (L < D && ww < P.T[L + 1]) ++L;
+  uint32_t L = 0;
+  for (uint32_t k0 = 1; k0 <= D; k0 += 64) {
+    const uint32_t k = k0 + lane;
+    const bool in = k <= D && ww < P.T[k];
+    const uint32_t n = static_cast<uint32_t>(__popcll(__ballot(in)));
+    L += n;
+    if (n < 64) break;
+  }
   return L;
 }
 

@@ -38,7 +38,7 @@ struct alignas(16) GenMin {
 struct alignas(64) RunDev {
   int64_t N, D, ld;       // ld: row pitch in elements (multiple of 32)
   double F, CR;
-  double inv_ln_cr;       // 1 / ln(CR) for the NEC length estimate (0 if CR in {0,1})
+  double inv_ln_cr;       // 1 / ln(CR), 0 when CR is 0 or 1 (NEC length short-cut)
   uint64_t thr;           // number of 32-bit words w with (w + 1/2) 2^-32 < CR
   float Ff, pad0;
   uint32_t key0, key1, run_id;

@@ -189,6 +189,8 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   R.F = sizeof(T) == 4 ? static_cast<T>(P.Ff) : static_cast<T>(P.F);
   const uint32_t N = static_cast<uint32_t>(P.N);
   const int64_t ld = P.ld;
+  T* fit = static_cast<T*>(const_cast<void*>(P.fit));
+  const T fold = FN != FN_NONE ? fit[i] : T(0);  // only row i's block writes it
 
   // Alg 2 line 6 and the index draws of Alg 6: base r0, difference r1 - r2.
   uint32_t r0, r1, r2;
@@ -301,11 +303,10 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
 
   if (!live) return;
   const T fu = canon(tot);
-  T* fit = static_cast<T*>(const_cast<void*>(P.fit));
   bool win = true;
   if constexpr (FN != FN_NONE) {
     // Alg 1 line 10 / Alg 2 line 11: strictly lower fitness replaces.
-    win = fu < fit[i];
+    win = fu < fold;
   }
   if (win) {
 #pragma unroll
