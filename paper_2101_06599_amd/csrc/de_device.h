@@ -9,6 +9,24 @@
 
 namespace de {
 
+// Pointers into device memory are carried as generic pointers in the run
+// records; re-qualifying them as global lets the compiler use global (not
+// flat) memory instructions, whose loads it can keep in flight together.
+// (The host compilation pass only parses device code; it sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define DE_GLOBAL __attribute__((address_space(1)))
+#else
+#define DE_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ const DE_GLOBAL T* gconst(const void* p) {
+  return (const DE_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ DE_GLOBAL T* gmut(void* p) {
+  return (DE_GLOBAL T*)p;
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten S-box rounds on a
 // 128-bit counter; each round multiplies words 0 and 2 by the two Philox
 // constants, and the two-word key advances by the Weyl constants between
@@ -77,10 +95,11 @@ __device__ __forceinline__ uint32_t nec_length(const RunDev& P, uint32_t w) {
   if (P.inv_ln_cr == 0.0) return P.CR >= 1.0 ? D : 1u;
   const uint32_t lane = __lane_id();
   const uint64_t ww = w;
+  const DE_GLOBAL uint64_t* T = gconst<uint64_t>(P.T);
   uint32_t L = 0;
   for (uint32_t k0 = 1; k0 <= D; k0 += 64) {
     const uint32_t k = k0 + lane;
-    const bool in = k <= D && ww < P.T[k];
+    const bool in = k <= D && ww < T[k];
     const uint32_t n = static_cast<uint32_t>(__popcll(__ballot(in)));
     L += n;
     if (n < 64) break;

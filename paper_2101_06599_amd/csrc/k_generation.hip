@@ -17,34 +17,38 @@ namespace de {
 template <typename T> struct V4 { T v[4]; };
 
 template <typename T>
-__device__ __forceinline__ V4<T> load4(const T* p) {
+__device__ __forceinline__ V4<T> load4(const DE_GLOBAL T* p) {
   V4<T> r;
   if constexpr (sizeof(T) == 4) {
-    const float4 f = *reinterpret_cast<const float4*>(p);
+    const float4 f = *(const DE_GLOBAL float4*)p;
     r.v[0] = f.x; r.v[1] = f.y; r.v[2] = f.z; r.v[3] = f.w;
   } else {
-    const double2 a = reinterpret_cast<const double2*>(p)[0];
-    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    const double2 a = ((const DE_GLOBAL double2*)p)[0];
+    const double2 b = ((const DE_GLOBAL double2*)p)[1];
     r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
   }
   return r;
 }
 
 template <typename T>
-__device__ __forceinline__ void store4(T* p, const T (&u)[4]) {
+__device__ __forceinline__ void store4(DE_GLOBAL T* p, const T (&u)[4]) {
   if constexpr (sizeof(T) == 4) {
-    *reinterpret_cast<float4*>(p) = make_float4(u[0], u[1], u[2], u[3]);
+    *(DE_GLOBAL float4*)p = make_float4(u[0], u[1], u[2], u[3]);
   } else {
-    reinterpret_cast<double2*>(p)[0] = make_double2(u[0], u[1]);
-    reinterpret_cast<double2*>(p)[1] = make_double2(u[2], u[3]);
+    ((DE_GLOBAL double2*)p)[0] = make_double2(u[0], u[1]);
+    ((DE_GLOBAL double2*)p)[1] = make_double2(u[2], u[3]);
   }
 }
 
 // Everything a row needs, gathered once per row (all wave-uniform).
 template <typename T>
 struct RowCtx {
-  const T* xi; const T* x0; const T* x1; const T* x2; const T* o;
-  T* dst;
+  const DE_GLOBAL T* xi;
+  const DE_GLOBAL T* x0;
+  const DE_GLOBAL T* x1;
+  const DE_GLOBAL T* x2;
+  const DE_GLOBAL T* o;
+  DE_GLOBAL T* dst;
   T F;
   uint64_t thr;
   uint32_t D, jr, L, g, i;
@@ -54,10 +58,9 @@ struct RowCtx {
 // Chunk c of the trial row: mask bits (bit v = element 4c+v crosses) and the
 // four trial values.  Elements at or beyond D keep the parent's (padding).
 template <typename T>
-__device__ __forceinline__ uint32_t build_chunk(const RunDev& P, const RowCtx<T>& R, uint32_t c,
-                                                T (&u)[4]) {
+__device__ __forceinline__ uint32_t build_chunk_from(const RunDev& P, const RowCtx<T>& R,
+                                                     uint32_t c, const V4<T>& x, T (&u)[4]) {
   const uint32_t j0 = 4 * c;
-  const V4<T> x = load4(R.xi + j0);
   uint32_t m = 0;
   if (R.xo == XO_BIN) {
     const uint4 b = draw(P, TAG_BIN, R.g, R.i, c);
@@ -87,6 +90,12 @@ __device__ __forceinline__ uint32_t build_chunk(const RunDev& P, const RowCtx<T>
   return m;
 }
 
+template <typename T>
+__device__ __forceinline__ uint32_t build_chunk(const RunDev& P, const RowCtx<T>& R, uint32_t c,
+                                                T (&u)[4]) {
+  return build_chunk_from(P, R, c, load4(R.xi + 4 * c), u);
+}
+
 // Trial value of a single element j (used only past the register-cached part
 // of very long rows, for the Rosenbrock neighbour of a chunk's last element).
 template <typename T>
@@ -106,7 +115,7 @@ __device__ __forceinline__ T trial_elem(const RunDev& P, const RowCtx<T>& R, uin
 // chunk (the pair that crosses into the next chunk is added separately).
 template <typename T, int FN>
 __device__ __forceinline__ T chunk_terms(const RowCtx<T>& R, uint32_t c, const T (&u)[4],
-                                         T& zfirst) {
+                                         const V4<T>& o, T& zfirst) {
   const uint32_t j0 = 4 * c;
   T acc = T(0);
   if constexpr (FN == FN_SPHERE) {
@@ -114,12 +123,10 @@ __device__ __forceinline__ T chunk_terms(const RowCtx<T>& R, uint32_t c, const T
     for (int v = 0; v < 4; ++v)
       if (j0 + v < R.D) acc += point_term<T, FN>(u[v], T(0));
   } else if constexpr (FN == FN_RASTRIGIN) {
-    const V4<T> o = load4(R.o + j0);
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       if (j0 + v < R.D) acc += point_term<T, FN>(u[v], o.v[v]);
   } else if constexpr (FN == FN_ROSENBROCK) {
-    const V4<T> o = load4(R.o + j0);
     T z[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) z[v] = (u[v] - o.v[v]) + T(1);
@@ -133,22 +140,22 @@ __device__ __forceinline__ T chunk_terms(const RowCtx<T>& R, uint32_t c, const T
 
 template <typename T>
 __device__ __forceinline__ T runtime_terms(int fn, const RowCtx<T>& R, uint32_t c, const T (&u)[4],
-                                           T& zf) {
-  if (fn == FN_SPHERE) return chunk_terms<T, FN_SPHERE>(R, c, u, zf);
-  if (fn == FN_RASTRIGIN) return chunk_terms<T, FN_RASTRIGIN>(R, c, u, zf);
-  return chunk_terms<T, FN_ROSENBROCK>(R, c, u, zf);
+                                           const V4<T>& o, T& zf) {
+  if (fn == FN_SPHERE) return chunk_terms<T, FN_SPHERE>(R, c, u, o, zf);
+  if (fn == FN_RASTRIGIN) return chunk_terms<T, FN_RASTRIGIN>(R, c, u, o, zf);
+  return chunk_terms<T, FN_ROSENBROCK>(R, c, u, o, zf);
 }
 
 template <int TPR> struct Shape {
   static constexpr int BS = TPR >= 256 ? TPR : 256;  // threads per block
   static constexpr int RPB = BS / TPR;               // rows per block
   static constexpr int NW = TPR / 64;                // wavefronts per row
-  // wide rows: ask for 8 waves per SIMD (<= 64 VGPRs) so that two rows'
-  // blocks share a CU; narrow rows keep the compiler's choice
-  static constexpr int MINW = 1;
   // chunks of 4 elements held in registers per thread: D <= 16 * TPR (20 * 512
   // for 512-wide rows) stays in registers between evaluation and write-back
   static constexpr int MAXIT = TPR == 512 ? 5 : 4;
+  // 64-lane rows issue every cached chunk's parent loads before using any
+  // (more loads in flight per wave); wide rows would lose occupancy to it
+  static constexpr bool PREFETCH = TPR == 64;
 };
 
 // FN: a fixed function, FN_ANY (taken from the run record) or FN_NONE (build
@@ -156,7 +163,7 @@ template <int TPR> struct Shape {
 // XO: a fixed crossover or XO_ANY.  BATCH: rows come from a row map that
 // spans several runs.
 template <typename T, int FN, int XO, int TPR, int MAXIT, bool BATCH>
-__global__ void __launch_bounds__(Shape<TPR>::BS, Shape<TPR>::MINW)
+__global__ void __launch_bounds__(Shape<TPR>::BS)
 k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* __restrict__ rowmap,
              int64_t rows, uint32_t gnew) {
   using S = Shape<TPR>;
@@ -189,7 +196,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   R.F = sizeof(T) == 4 ? static_cast<T>(P.Ff) : static_cast<T>(P.F);
   const uint32_t N = static_cast<uint32_t>(P.N);
   const int64_t ld = P.ld;
-  T* fit = static_cast<T*>(const_cast<void*>(P.fit));
+  DE_GLOBAL T* fit = gmut<T>(P.fit);
   const T fold = FN != FN_NONE ? fit[i] : T(0);  // only row i's block writes it
 
   // Alg 2 line 6 and the index draws of Alg 6: base r0, difference r1 - r2.
@@ -203,8 +210,8 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   else if (R.xo == XO_EXP) R.L = P.exp_impl == EXPI_SCAN ? exp_length_scan(P, R.g, i)
                                                           : exp_length_serial(P, R.g, i);
 
-  const uint8_t* cur = P.flags + ((R.g - 1) & 1u) * static_cast<int64_t>(N);
-  uint8_t* nxt = P.flags + (R.g & 1u) * static_cast<int64_t>(N);
+  const DE_GLOBAL uint8_t* cur = gconst<uint8_t>(P.flags) + ((R.g - 1) & 1u) * static_cast<int64_t>(N);
+  DE_GLOBAL uint8_t* nxt = gmut<uint8_t>(P.flags) + (R.g & 1u) * static_cast<int64_t>(N);
   // wave-uniform by construction; keep them (and the row pointers) scalar
   r0 = __builtin_amdgcn_readfirstlane(r0);
   r1 = __builtin_amdgcn_readfirstlane(r1);
@@ -215,12 +222,12 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   const uint32_t c0 = __builtin_amdgcn_readfirstlane(cur[r0]);
   const uint32_t c1 = __builtin_amdgcn_readfirstlane(cur[r1]);
   const uint32_t c2 = __builtin_amdgcn_readfirstlane(cur[r2]);
-  R.xi = static_cast<const T*>(P.X[ci]) + static_cast<int64_t>(i) * ld;
-  R.x0 = static_cast<const T*>(P.X[c0]) + static_cast<int64_t>(r0) * ld;
-  R.x1 = static_cast<const T*>(P.X[c1]) + static_cast<int64_t>(r1) * ld;
-  R.x2 = static_cast<const T*>(P.X[c2]) + static_cast<int64_t>(r2) * ld;
-  R.o = static_cast<const T*>(P.o);
-  R.dst = static_cast<T*>(P.X[ci ^ 1u]) + static_cast<int64_t>(i) * ld;
+  R.xi = gconst<T>(P.X[ci]) + static_cast<int64_t>(i) * ld;
+  R.x0 = gconst<T>(P.X[c0]) + static_cast<int64_t>(r0) * ld;
+  R.x1 = gconst<T>(P.X[c1]) + static_cast<int64_t>(r1) * ld;
+  R.x2 = gconst<T>(P.X[c2]) + static_cast<int64_t>(r2) * ld;
+  R.o = gconst<T>(P.o);
+  R.dst = gmut<T>(P.X[ci ^ 1u]) + static_cast<int64_t>(i) * ld;
 
   const uint32_t nchunk = (R.D + 3) >> 2;
   const bool tracing = P.tr_idx != nullptr || P.tr_mask != nullptr || P.tr_trial != nullptr;
@@ -232,16 +239,37 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
 
   // Alg 2 lines 8-10 for this row: trial = parent with the masked elements
   // replaced by x_r0 + F (x_r1 - x_r2), evaluated on the fly.
+  // Phase 1 (64-lane rows): every cached chunk's parent (and shift) loads go
+  // out together; wide rows load each chunk as they reach it.
+  constexpr bool kShift = FN == FN_RASTRIGIN || FN == FN_ROSENBROCK || FN == FN_ANY;
+  const bool shifted = kShift && (FN != FN_ANY || fn != FN_SPHERE);
+  V4<T> xs[MAXIT], os[MAXIT];
+  if constexpr (S::PREFETCH) {
+#pragma unroll
+    for (int k = 0; k < MAXIT; ++k) {
+      const uint32_t c = k * TPR + t;
+      if (c < nchunk) {
+        xs[k] = load4(R.xi + 4 * c);
+        if (shifted) os[k] = load4(R.o + 4 * c);
+      }
+    }
+  }
+  // Phase 2: mask, donors where the mask is set, trial and fitness terms.
 #pragma unroll
   for (int k = 0; k < MAXIT; ++k) {
     const uint32_t c = k * TPR + t;
     mb[k] = 0;
     if (c < nchunk) {
-      mb[k] = build_chunk(P, R, c, u[k]);
+      if constexpr (!S::PREFETCH) {
+        xs[k] = load4(R.xi + 4 * c);
+        if (shifted) os[k] = load4(R.o + 4 * c);
+      }
+      mb[k] = build_chunk_from(P, R, c, xs[k], u[k]);
       cnt += __popc(mb[k]);
       if constexpr (FN != FN_NONE) {
         T zf = T(0);
-        acc += FN == FN_ANY ? runtime_terms(fn, R, c, u[k], zf) : chunk_terms<T, FN>(R, c, u[k], zf);
+        acc += FN == FN_ANY ? runtime_terms(fn, R, c, u[k], os[k], zf)
+                            : chunk_terms<T, FN>(R, c, u[k], os[k], zf);
         if constexpr (FN == FN_ROSENBROCK || FN == FN_ANY) zrow[c] = zf;
       }
     }
@@ -253,7 +281,10 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
     cnt += __popc(m);
     if constexpr (FN != FN_NONE) {
       T zf = T(0);
-      acc += FN == FN_ANY ? runtime_terms(fn, R, c, v, zf) : chunk_terms<T, FN>(R, c, v, zf);
+      V4<T> ov;
+      if (kShift && (FN != FN_ANY || fn != FN_SPHERE)) ov = load4(R.o + 4 * c);
+      acc += FN == FN_ANY ? runtime_terms(fn, R, c, v, ov, zf)
+                          : chunk_terms<T, FN>(R, c, v, ov, zf);
       if ((FN == FN_ROSENBROCK || (FN == FN_ANY && fn == FN_ROSENBROCK)) && 4 * c + 4 < R.D) {
         const T zn = (trial_elem(P, R, 4 * c + 4) - R.o[4 * c + 4]) + T(1);
         const T zl = (v[3] - R.o[4 * c + 3]) + T(1);
@@ -325,8 +356,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
       nxt[i] = static_cast<uint8_t>(win ? ci ^ 1u : ci);
       if (win) fit[i] = fu;
       // deferred best-so-far: winners' new fitness, +inf for the others
-      static_cast<T*>(P.hist)[static_cast<int64_t>(gnew % kHist) * N + i] =
-          win ? fu : Math<T>::inf();
+      gmut<T>(P.hist)[static_cast<int64_t>(gnew % kHist) * N + i] = win ? fu : Math<T>::inf();
     }
   }
 
