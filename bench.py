@@ -93,9 +93,12 @@ def winners(gpu, K, run=0):
     return wins / (K * len(f0))
 
 
-def run_variant(cfg, K, W, prof_K):
+def run_variant(cfg, K, W, prof_K, graph=False):
+    """Times K generations (direct launches, or replayed 64-generation graphs
+    when `graph`), then the main kernel's average duration with events."""
     import paper_2101_06599_amd as de
     gpu = de.DE([cfg])
+    gpu.graph(graph)
     gpu.generation(W)
     ms = time_gens(gpu, K)
     kms = kernel_ms(gpu, prof_K)
@@ -153,7 +156,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections", default="all",
                     help="comma list of: head (headline only), variants, rosenbrock, rotated, "
-                         "batched, cpu, copy (default: all but copy)")
+                         "batched, tuning, cpu, copy (default: all but copy)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -167,13 +170,15 @@ def main():
     torch.cuda.set_device(0)
     de.lib()
     secs = set(args.sections.split(",")) if args.sections != "all" else {
-        "variants", "rosenbrock", "rotated", "batched", "cpu"}
+        "variants", "rosenbrock", "rotated", "batched", "tuning", "cpu"}
     K, W = args.steps, args.warmup
 
     head = dict(synth.RASTRIGIN_D1000, xo="nec", dtype="fp64")
     gpu, h = run_variant(head, K, W, prof_K=min(K, 200))
     win = winners(gpu, 20)
     gpu.close()
+    g_graph, h_graph = run_variant(head, K, W, prof_K=10, graph=True)
+    g_graph.close()
     N, D, CR = head["N"], head["D"], head["CR"]
     ab = alg_bytes("nec", N, D, CR, 8)
     achieved = ab / (h["kernel_ms"] * 1e-3) / 1e9
@@ -185,7 +190,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "shifted Rastrigin, D=1000, N=2048, F=0.5, CR=0.9, "
                                "DE/rand/1/NEC, FP64, x~U[-5.12,5.12], o~U[-4,4], Philox seed 0",
-                   "N": N, "D": D, "generation": "one generation per step"},
+                   "N": N, "D": D, "generation": "one generation per step",
+                   "launch": "one kernel per generation, stream-ordered"},
+        "graph_replay_ms_per_step": h_graph["ms_per_gen"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_generation<double, RASTRIGIN, NEC>",
@@ -258,6 +265,16 @@ def main():
             "pop_dim_gen_s": elems * kb / (ms / 1e3),
             "hbm_frac_kernel": byt / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         g2.close()
+
+    if "tuning" in secs:
+        from paper_2101_06599_amd.tune import tune_tpr
+        tun = {}
+        for name, cfg in (("rastrigin_d1000_n2048_nec_fp64", head),
+                          ("rosenbrock_d10000_n8192_nec_fp32",
+                           dict(synth.ROSENBROCK_D10000, xo="nec"))):
+            best, table = tune_tpr(cfg, gens=64, use_cache=False)
+            tun[name] = {"best_tpr": best, "ms_per_gen_by_tpr": table}
+        out["tuning"] = tun
 
     if "copy" in secs:
         # counter calibration: an elementwise kernel that reads and writes a

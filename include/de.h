@@ -97,7 +97,9 @@ typedef struct {
   int32_t dtype;    /* de_dtype of population and trial arithmetic */
   int32_t mm;       /* de_matmul, ELLIPSOID_ROT only (ignored otherwise) */
   int32_t exp_impl; /* de_exp_impl, DE_XO_EXP only */
-  int32_t reserved; /* must be 0 */
+  int32_t tpr;      /* lanes per individual in the generation kernel: 0 = chosen
+                       from D; 64, 256, 512 or 1024 forces it (batched: 0 or 64).
+                       Results do not depend on it. */
   double lo, hi;    /* initial population drawn uniformly from [lo, hi]^D, lo < hi */
   double olo, ohi;  /* shift o drawn uniformly from [olo, ohi]^D when shift == NULL */
   uint64_t seed;    /* Philox key */
@@ -167,6 +169,13 @@ de_status de_trace(de_handle* h, int32_t run, int64_t* idx, uint8_t* mask, void*
  * of main-kernel launches they cover. */
 de_status de_profile(de_handle* h, int32_t enable);
 de_status de_profile_read(de_handle* h, double* main_ms, int64_t* main_launches);
+
+/* Graph replay: while enabled, de_generation runs whole blocks of 64
+ * generations (with their best-so-far update) by launching one HIP graph,
+ * captured on first use, instead of launching each kernel; the remaining
+ * generations of a call are launched directly.  Results are identical either
+ * way.  Ignored while kernel timing (de_profile) is on. */
+de_status de_graph(de_handle* h, int32_t enable);
 
 /* Message for the last failed call on h (or on a NULL handle); valid until
  * the next call on the same handle. */

@@ -25,7 +25,7 @@ MM = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 
 ABI_FUNCTIONS = ("de_workspace_size", "de_init", "de_generation", "de_evaluate", "de_best",
                  "de_get_state", "de_set_state", "de_trace", "de_profile", "de_profile_read",
-                 "de_last_error", "de_destroy")
+                 "de_graph", "de_last_error", "de_destroy")
 
 
 class DEError(RuntimeError):
@@ -38,7 +38,7 @@ class RunDesc(C.Structure):
     """Mirror of ``de_run_desc``."""
     _fields_ = [("N", C.c_int64), ("D", C.c_int64), ("F", C.c_double), ("CR", C.c_double),
                 ("xo", C.c_int32), ("fn", C.c_int32), ("dtype", C.c_int32), ("mm", C.c_int32),
-                ("exp_impl", C.c_int32), ("reserved", C.c_int32),
+                ("exp_impl", C.c_int32), ("tpr", C.c_int32),
                 ("lo", C.c_double), ("hi", C.c_double), ("olo", C.c_double), ("ohi", C.c_double),
                 ("seed", C.c_uint64), ("shift", C.c_void_p), ("rot", C.c_void_p)]
 
@@ -65,6 +65,7 @@ def lib():
         L.de_trace.argtypes = [vp, i32, vp, vp, vp, vp]
         L.de_profile.argtypes = [vp, i32]
         L.de_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
+        L.de_graph.argtypes = [vp, i32]
         L.de_last_error.argtypes = [vp]
         L.de_last_error.restype = C.c_char_p
         L.de_destroy.argtypes = [vp]
@@ -84,7 +85,7 @@ def _desc(run: dict, keep: list) -> RunDesc:
         N=int(run["N"]), D=int(run["D"]), F=float(run.get("F", 0.5)), CR=float(run.get("CR", 0.9)),
         xo=XO[run.get("xo", "bin")], fn=FN[run.get("fn", "sphere")],
         dtype=DTYPE[run.get("dtype", "fp64")], mm=MM[run.get("mm", "fp64")],
-        exp_impl=EXP_IMPL[run.get("exp_impl", "lane")], reserved=0,
+        exp_impl=EXP_IMPL[run.get("exp_impl", "lane")], tpr=int(run.get("tpr", 0)),
         lo=float(run.get("lo", -100.0)), hi=float(run.get("hi", 100.0)),
         olo=float(run.get("olo", 0.0)), ohi=float(run.get("ohi", 0.0)),
         seed=int(run.get("seed", 0)),
@@ -114,11 +115,14 @@ class DE:
     lo, hi, olo, ohi, seed and optional device tensors shift (D values of the
     run's dtype) and rot (D x D float64, rotated function only)."""
 
-    def __init__(self, runs: list[dict], device: str = "cuda:0"):
+    def __init__(self, runs: list[dict], device: str = "cuda:0", tune: bool = False):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.runs = [dict(r) for r in runs]
+        if tune and len(self.runs) == 1 and not self.runs[0].get("tpr"):
+            from .tune import tune_tpr
+            self.runs[0]["tpr"], self.tuning = tune_tpr(self.runs[0])
         self._keep: list = []
         descs = [_desc(r, self._keep) for r in self.runs]
         self._arr = (RunDesc * len(descs))(*descs)
@@ -212,6 +216,10 @@ class DE:
         n = C.c_int64(0)
         self._check(lib().de_profile_read(self._h, C.byref(ms), C.byref(n)), self._h)
         return ms.value, n.value
+
+    def graph(self, enable: bool = True):
+        """Replay captured 64-generation graphs in generation() (same results)."""
+        self._check(lib().de_graph(self._h, 1 if enable else 0), self._h)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -67,6 +67,18 @@ struct alignas(64) RunDev {
   void* tr_ftrial;
 };
 
+// Handle generation number of a launch: `g` itself, or *base + g when the
+// launch belongs to a captured graph that is replayed (the graph's last
+// kernel advances *base on the device).
+struct GenNo {
+  uint32_t g;
+  uint32_t pad;
+  const uint32_t* base;
+};
+__device__ __forceinline__ uint32_t gen_value(const GenNo& n) {
+  return n.base ? *n.base + n.g : n.g;
+}
+
 // ---- launch helpers implemented in the kernel translation units ---------
 struct GenLaunch {
   const RunDev* runs;     // device array
@@ -75,7 +87,7 @@ struct GenLaunch {
   const uint2* rowmap;    // batched: global row -> (run, row)
   int64_t rows;           // rows in this launch
   int32_t tpr;            // threads per row
-  uint32_t gnew;          // handle generation being computed
+  GenNo gnew;             // handle generation being computed
   hipStream_t s;
 };
 
@@ -88,12 +100,14 @@ hipError_t launch_init_impl(const RunDev* runs, const RunDev& h, int run, double
 hipError_t launch_eval_pop(const RunDev* runs, const RunDev& h, int run, hipStream_t s);
 hipError_t launch_best_init(const RunDev* runs, int n_runs, hipStream_t s);
 // best-so-far over the deferred generations [gfirst, gfirst + count)
-hipError_t launch_best_flush(const RunDev* runs, int n_runs, int64_t max_rows, uint32_t gfirst,
-                             int count, hipStream_t s);
-hipError_t launch_generation(const GenLaunch& L, int fn, int xo, int dtype, bool batched);
-hipError_t launch_pexp_trial(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+hipError_t launch_best_flush(const RunDev* runs, int n_runs, GenNo gfirst, int count,
                              hipStream_t s);
-hipError_t launch_eval_select(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+// *base = v, or *base += v (graph bookkeeping)
+hipError_t launch_gen_base(uint32_t* base, uint32_t v, bool add, hipStream_t s);
+hipError_t launch_generation(const GenLaunch& L, int fn, int xo, int dtype, bool batched);
+hipError_t launch_pexp_trial(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
+                             hipStream_t s);
+hipError_t launch_eval_select(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
                               hipStream_t s);
 hipError_t launch_eval_rows(const RunDev& h, const void* X, int64_t rows, int64_t ldx, void* out,
                             hipStream_t s);
@@ -106,9 +120,9 @@ hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
 // N rows (the trials of the coming generation when `trials`, else the
 // population) into fit_dst or, when select, straight into greedy selection.
 hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s);
-hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
                               hipStream_t s);
-hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
                              hipStream_t s);
 hipError_t launch_rot_init_fit(const RunDev* runs, const RunDev& h, int run, hipStream_t s);
 hipError_t launch_rot_eval_rows(const RunDev* runs, const RunDev& h, int run, const void* X,

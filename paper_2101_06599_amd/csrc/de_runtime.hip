@@ -26,6 +26,12 @@ struct de_handle {
   RunDev* dev_runs = nullptr;
   BestState* best = nullptr;
   double* scratch_f64 = nullptr;     // one FP64 for de_best
+  uint32_t* gbase = nullptr;         // device generation base read by graph replays
+  bool graph_on = false;             // replay captured blocks of kHist generations
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool base_valid = false;           // device *gbase equals base_value
+  uint32_t base_value = 0;
   uint2* rowmap = nullptr;
   int64_t total_rows = 0;
   std::vector<uint2> rowmap_host;
@@ -115,7 +121,9 @@ de_status validate(const de_run_desc* runs, int32_t n_runs, std::string& msg) {
     if (d.xo < DE_XO_BIN || d.xo > DE_XO_NEC) return bad("unknown crossover");
     if (d.fn < DE_FN_SPHERE || d.fn > DE_FN_ELLIPSOID_ROT) return bad("unknown function");
     if (d.exp_impl < DE_EXP_LANE || d.exp_impl > DE_EXP_SCAN) return bad("unknown exp_impl");
-    if (d.reserved != 0) return bad("reserved must be 0");
+    if (d.tpr != 0 && d.tpr != 64 && d.tpr != 256 && d.tpr != 512 && d.tpr != 1024)
+      return bad("tpr must be 0, 64, 256, 512 or 1024");
+    if (n_runs > 1 && d.tpr != 0 && d.tpr != 64) return bad("batched runs use tpr 0 or 64");
     if (d.fn != DE_FN_SPHERE && !d.shift &&
         !(std::isfinite(d.olo) && std::isfinite(d.ohi) && d.olo <= d.ohi))
       return bad("need finite olo <= ohi when shift is NULL");
@@ -194,10 +202,8 @@ Layout layout(const de_run_desc* runs, int32_t n_runs) {
 
 int pick_tpr(const de_run_desc& d, bool batched) {
   if (batched) return 64;
-  if (const char* e = std::getenv("DE_TPR")) {
-    int v = std::atoi(e);
-    if (v == 64 || v == 256 || v == 512 || v == 1024) return v;
-  }
+  if (d.tpr != 0) return d.tpr;
+  // measured defaults: a row held in registers by as few lanes as fit
   const int64_t nchunk = (d.D + 3) / 4;
   if (nchunk <= 64 * 4) return 64;
   if (nchunk <= 256 * 4) return 256;
@@ -226,14 +232,15 @@ void add_pair_count(de_handle* h, int64_t n) {
 de_status flush_best(de_handle* h, hipStream_t s) {
   if (h->pending == 0) return DE_OK;
   const uint32_t gfirst = h->done - static_cast<uint32_t>(h->pending) + 1;
-  HIPCHECK(h, de::launch_best_flush(h->dev_runs, h->n_runs, 0, gfirst, h->pending, s));
+  HIPCHECK(h, de::launch_best_flush(h->dev_runs, h->n_runs, de::GenNo{gfirst, 0, nullptr},
+                                    h->pending, s));
   h->pending = 0;
   return DE_OK;
 }
 
 // The launches of one generation of one run (single-run handles) or of all
 // runs (batched); `mark` brackets the dominant kernel with events if enabled.
-de_status one_generation(de_handle* h, hipStream_t s) {
+de_status generation_launches(de_handle* h, hipStream_t s, de::GenNo gnew) {
   // per-launch event pairs only where a generation has several kernels; a
   // one-kernel generation is timed as a span of launches in de_generation
   auto mark = [&]() {
@@ -242,7 +249,6 @@ de_status one_generation(de_handle* h, hipStream_t s) {
     if (e) (void)hipEventRecord(e, s);
     add_pair_count(h, 1);
   };
-  const uint32_t gnew = h->done + 1;
   if (h->batched) {
     de::GenLaunch L{h->dev_runs, h->host.data(), 0, h->rowmap, h->total_rows, 64, gnew, s};
     mark();
@@ -277,8 +283,47 @@ de_status one_generation(de_handle* h, hipStream_t s) {
       }
     }
   }
+  return DE_OK;
+}
+
+de_status one_generation(de_handle* h, hipStream_t s) {
+  const uint32_t gnew = h->done + 1;
+  de_status st = generation_launches(h, s, de::GenNo{gnew, 0, nullptr});
+  if (st != DE_OK) return st;
   h->done = gnew;
   if (++h->pending == de::kHist) return flush_best(h, s);
+  return DE_OK;
+}
+
+// Captures kHist generations, their best-so-far update and the advance of the
+// device generation base into one graph (on a private stream; the graph is
+// then launched on the caller's stream).  Generation numbers inside are
+// *gbase + 1 .. *gbase + kHist.
+de_status capture_block(de_handle* h) {
+  if (!h->cap_stream) HIPCHECK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = h->cap_stream;
+  HIPCHECK(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  de_status st = DE_OK;
+  for (int k = 1; k <= de::kHist && st == DE_OK; ++k)
+    st = generation_launches(h, cs, de::GenNo{static_cast<uint32_t>(k), 0, h->gbase});
+  hipError_t e = hipSuccess;
+  if (st == DE_OK)
+    e = de::launch_best_flush(h->dev_runs, h->n_runs, de::GenNo{1, 0, h->gbase}, de::kHist, cs);
+  if (st == DE_OK && e == hipSuccess) e = de::launch_gen_base(h->gbase, de::kHist, true, cs);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(cs, &g);
+  if (st != DE_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "launch during graph capture");
+  if (e2 != hipSuccess) return hip_fail(h, e2, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->gexec = nullptr;
+    return hip_fail(h, e, "hipGraphInstantiate");
+  }
   return DE_OK;
 }
 
@@ -324,6 +369,7 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
   h->dev_runs = reinterpret_cast<RunDev*>(ws + L.runs_off);
   h->best = reinterpret_cast<BestState*>(ws + L.best_off);
   h->scratch_f64 = reinterpret_cast<double*>(ws + L.scratch_off);
+  h->gbase = reinterpret_cast<uint32_t*>(ws + L.scratch_off + 16);
   h->rowmap = h->batched ? reinterpret_cast<uint2*>(ws + L.rowmap_off) : nullptr;
   h->host.resize(n_runs);
   h->tables.resize(n_runs);
@@ -433,7 +479,30 @@ de_status de_generation(de_handle* h, int32_t n_gens, void* stream) {
     hipEvent_t e = next_event(h);
     if (e) (void)hipEventRecord(e, s);
   }
-  for (int32_t k = 0; k < n_gens; ++k) {
+  int32_t left = n_gens;
+  if (h->graph_on && !h->prof && left >= de::kHist) {
+    // whole blocks of kHist generations start on a flushed best-so-far
+    while (left > 0 && h->pending != 0) {
+      de_status st = one_generation(h, s);
+      if (st != DE_OK) return st;
+      --left;
+    }
+    while (left >= de::kHist) {
+      if (!h->gexec) {
+        de_status st = capture_block(h);
+        if (st != DE_OK) return st;
+      }
+      if (!h->base_valid || h->base_value != h->done) {
+        HIPCHECK(h, de::launch_gen_base(h->gbase, h->done, false, s));
+        h->base_valid = true;
+      }
+      HIPCHECK(h, hipGraphLaunch(h->gexec, s));
+      h->done += de::kHist;
+      h->base_value = h->done;
+      left -= de::kHist;
+    }
+  }
+  for (int32_t k = 0; k < left; ++k) {
     de_status st = one_generation(h, s);
     if (st != DE_OK) return st;
   }
@@ -600,8 +669,16 @@ const char* de_last_error(const de_handle* h) {
   return g_err.c_str();
 }
 
+de_status de_graph(de_handle* h, int32_t enable) {
+  if (!h) return fail(nullptr, DE_E_INVALID, "NULL handle");
+  h->graph_on = enable != 0;
+  return DE_OK;
+}
+
 void de_destroy(de_handle* h) {
   if (!h) return;
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
 }

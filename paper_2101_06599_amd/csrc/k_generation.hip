@@ -165,7 +165,7 @@ template <int TPR> struct Shape {
 template <typename T, int FN, int XO, int TPR, int MAXIT, bool BATCH>
 __global__ void __launch_bounds__(Shape<TPR>::BS)
 k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* __restrict__ rowmap,
-             int64_t rows, uint32_t gnew) {
+             int64_t rows, GenNo gn) {
   using S = Shape<TPR>;
   __shared__ T red[S::RPB * S::NW];
   __shared__ uint32_t redc[S::RPB * S::NW];
@@ -192,6 +192,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   R.D = static_cast<uint32_t>(P.D);
   R.thr = P.thr;
   R.i = i;
+  const uint32_t gnew = __builtin_amdgcn_readfirstlane(gen_value(gn));
   R.g = run_gen(P, gnew);
   R.F = sizeof(T) == 4 ? static_cast<T>(P.Ff) : static_cast<T>(P.F);
   const uint32_t N = static_cast<uint32_t>(P.N);

@@ -115,8 +115,9 @@ __global__ void __launch_bounds__(256) k_eval_rows(int fn, const T* __restrict__
 // selection (used after the job-per-individual exponential crossover).
 template <typename T>
 __global__ void __launch_bounds__(256) k_eval_select(const RunDev* __restrict__ runs, int32_t run,
-                                                     uint32_t gnew) {
+                                                     GenNo gn) {
   const RunDev& P = runs[run];
+  const uint32_t gnew = gen_value(gn);
   const uint32_t i = blockIdx.x;
   const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
   const uint32_t g = run_gen(P, gnew);
@@ -142,8 +143,9 @@ __global__ void __launch_bounds__(256) k_eval_select(const RunDev* __restrict__ 
 // uniform until a draw reaches Cr or the whole row is taken (lines 4-9).
 template <typename T>
 __global__ void __launch_bounds__(64) k_pexp_trial(const RunDev* __restrict__ runs, int32_t run,
-                                                   uint32_t gnew) {
+                                                   GenNo gn) {
   const RunDev& P = runs[run];
+  const uint32_t gnew = gen_value(gn);
   const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -237,9 +239,9 @@ __global__ void __launch_bounds__(256) k_best_init(const RunDev* __restrict__ ru
 // Deferred update, pass 1: the minimum over the rows each generation
 // replaced (block (k, run) handles generation gfirst + k of that run).
 __global__ void __launch_bounds__(256) k_best_gen_min(const RunDev* __restrict__ runs,
-                                                      uint32_t gfirst) {
+                                                      GenNo gfirst) {
   const RunDev& P = runs[blockIdx.y];
-  const uint32_t gnew = gfirst + blockIdx.x;
+  const uint32_t gnew = gen_value(gfirst) + blockIdx.x;
   const int64_t off = static_cast<int64_t>(gnew % kHist) * P.N;
   const GenMin m = P.dtype == 0 ? block_argmin(static_cast<const double*>(P.hist) + off, P.N)
                                 : block_argmin(static_cast<const float*>(P.hist) + off, P.N);
@@ -249,8 +251,9 @@ __global__ void __launch_bounds__(256) k_best_gen_min(const RunDev* __restrict__
 // Pass 2: walk the generations in order; a strictly lower minimum than the
 // best so far records that generation.  Between improvements every row keeps
 // f_i >= best, so the minimum over the replaced rows decides.
-__global__ void k_best_scan(const RunDev* __restrict__ runs, int n_runs, uint32_t gfirst,
+__global__ void k_best_scan(const RunDev* __restrict__ runs, int n_runs, GenNo gfirst_no,
                             int count) {
+  const uint32_t gfirst = gen_value(gfirst_no);
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_runs) return;
   const RunDev& P = runs[r];
@@ -331,6 +334,10 @@ __global__ void __launch_bounds__(256) k_normalize(const RunDev* __restrict__ ru
   if (threadIdx.x == 0) cur[i] = 0;
 }
 
+__global__ void k_gen_base(uint32_t* base, uint32_t v, int add) {
+  if (threadIdx.x == 0) *base = add ? *base + v : v;
+}
+
 __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e < n) p[e] = v;
@@ -373,14 +380,14 @@ hipError_t launch_eval_rows(const RunDev& h, const void* X, int64_t rows, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_eval_select(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+hipError_t launch_eval_select(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
                               hipStream_t s) {
   if (h.dtype == 0) hipLaunchKernelGGL(k_eval_select<double>, dim3(h.N), dim3(256), 0, s, runs, run, gnew);
   else hipLaunchKernelGGL(k_eval_select<float>, dim3(h.N), dim3(256), 0, s, runs, run, gnew);
   return hipGetLastError();
 }
 
-hipError_t launch_pexp_trial(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+hipError_t launch_pexp_trial(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
                              hipStream_t s) {
   if (h.dtype == 0) hipLaunchKernelGGL(k_pexp_trial<double>, dim3(nblk(h.N, 64)), dim3(64), 0, s, runs, run, gnew);
   else hipLaunchKernelGGL(k_pexp_trial<float>, dim3(nblk(h.N, 64)), dim3(64), 0, s, runs, run, gnew);
@@ -392,9 +399,8 @@ hipError_t launch_best_init(const RunDev* runs, int n_runs, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_best_flush(const RunDev* runs, int n_runs, int64_t max_rows, uint32_t gfirst,
-                             int count, hipStream_t s) {
-  (void)max_rows;
+hipError_t launch_best_flush(const RunDev* runs, int n_runs, GenNo gfirst, int count,
+                             hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_best_gen_min, dim3(count, n_runs), dim3(256), 0, s, runs, gfirst);
   hipLaunchKernelGGL(k_best_scan, dim3(nblk(n_runs, 256)), dim3(256), 0, s, runs, n_runs, gfirst,
@@ -413,6 +419,11 @@ hipError_t launch_normalize(const RunDev* runs, const RunDev& h, int run, uint32
                             hipStream_t s) {
   if (h.dtype == 0) hipLaunchKernelGGL(k_normalize<double>, dim3(h.N), dim3(256), 0, s, runs, run, gcur);
   else hipLaunchKernelGGL(k_normalize<float>, dim3(h.N), dim3(256), 0, s, runs, run, gcur);
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_base(uint32_t* base, uint32_t v, bool add, hipStream_t s) {
+  hipLaunchKernelGGL(k_gen_base, dim3(1), dim3(64), 0, s, base, v, add ? 1 : 0);
   return hipGetLastError();
 }
 

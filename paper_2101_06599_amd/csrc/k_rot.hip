@@ -63,6 +63,7 @@ __device__ __forceinline__ void split3(float v, __bf16& a, __bf16& b, __bf16& c)
 //   for src 1)
 template <typename T>
 __device__ __forceinline__ const T* a_row(const RunDev& P, int src, uint32_t gh, int64_t i) {
+  // (gh is uniform: the handle generation, resolved once per block)
   if (src == 2) return static_cast<const T*>(P.stage) + i * P.ld;
   const uint32_t N = static_cast<uint32_t>(P.N);
   const uint32_t g = run_gen(P, gh);
@@ -86,7 +87,8 @@ __device__ __forceinline__ void copy16(V* __restrict__ dst, const V* __restrict_
 // buffer, so one barrier per K step separates the two.
 template <int MODE>
 __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ runs, int32_t run,
-                                                 int src, uint32_t gh, int64_t rows) {
+                                                 int src, GenNo ghn, int64_t rows) {
+  const uint32_t gh = gen_value(ghn);
   using C = MM<MODE>;
   using T = typename C::T;
   using LT = typename C::L;
@@ -285,7 +287,8 @@ __device__ __forceinline__ T row_total(const RunDev& P, int64_t i, int ntn) {
 
 // Greedy selection on the trials of generation g (Alg 2 lines 11-14).
 template <typename T>
-__global__ void k_rot_select(const RunDev* __restrict__ runs, int32_t run, int ntn, uint32_t gnew) {
+__global__ void k_rot_select(const RunDev* __restrict__ runs, int32_t run, int ntn, GenNo gn) {
+  const uint32_t gnew = gen_value(gn);
   const RunDev& P = runs[run];
   const uint32_t N = static_cast<uint32_t>(P.N);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -380,7 +383,7 @@ hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s) {
   return hipGetLastError();
 }
 
-static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, uint32_t gh,
+static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, GenNo gh,
                        int64_t rows, hipStream_t s) {
   const int bm = tile_m_of(h.mm), bn = tile_n_of(h.mm);
   const int64_t blocks = ((rows + bm - 1) / bm) * ((h.D + bn - 1) / bn);
@@ -394,12 +397,12 @@ static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, ui
   return hipGetLastError();
 }
 
-hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
                               hipStream_t s) {
   return gemm(runs, h, run, 0, gnew, h.N, s);
 }
 
-hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, uint32_t gnew,
+hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
                              hipStream_t s) {
   const int ntn = static_cast<int>((h.D + tile_n_of(h.mm) - 1) / tile_n_of(h.mm));
   if (h.dtype == 0) hipLaunchKernelGGL(k_rot_select<double>, dim3(nb(h.N, 256)), dim3(256), 0, s, runs, run, ntn, gnew);
@@ -408,7 +411,7 @@ hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, uint3
 }
 
 hipError_t launch_rot_init_fit(const RunDev* runs, const RunDev& h, int run, hipStream_t s) {
-  hipError_t e = gemm(runs, h, run, 1, 0, h.N, s);
+  hipError_t e = gemm(runs, h, run, 1, GenNo{0, 0, nullptr}, h.N, s);
   if (e != hipSuccess) return e;
   const int ntn = static_cast<int>((h.D + tile_n_of(h.mm) - 1) / tile_n_of(h.mm));
   if (h.dtype == 0)
@@ -435,7 +438,7 @@ hipError_t launch_rot_eval_rows(const RunDev* runs, const RunDev& h, int run, co
     else
       hipLaunchKernelGGL(k_rot_stage<float>, dim3(nb(n * h.ld, 256)), dim3(256), 0, s,
                          static_cast<float*>(h.stage), h.ld, reinterpret_cast<const float*>(src), h.D, n);
-    hipError_t e = gemm(runs, h, run, 2, 0, n, s);
+    hipError_t e = gemm(runs, h, run, 2, GenNo{0, 0, nullptr}, n, s);
     if (e != hipSuccess) return e;
     if (h.dtype == 0)
       hipLaunchKernelGGL(k_rot_store<double>, dim3(nb(n, 256)), dim3(256), 0, s, runs, run, ntn, n,

@@ -118,11 +118,10 @@ def test_rosenbrock_d1000(dtype):
 # ---- launch shape does not change results ----------------------------------
 
 @pytest.mark.parametrize("cfg", [rast(N=40, D=999, xo="bin"), rosen(D=1001, N=20, xo="nec")])
-def test_row_width_invariance(cfg, monkeypatch):
+def test_row_width_invariance(cfg):
     outs = []
-    for tpr in ("64", "256", "1024"):
-        monkeypatch.setenv("DE_TPR", tpr)
-        gpu = DE([cfg])
+    for tpr in (64, 256, 512, 1024):
+        gpu = DE([dict(cfg, tpr=tpr)])
         tr = gpu.trace(0)
         gpu.generation(1)
         outs.append((tr["idx"].cpu().numpy().copy(), tr["trial"].cpu().numpy().copy(),
@@ -307,3 +306,50 @@ def test_full_size_rotated_4096x2048(mm, dtype):
     from paper_2101_06599_amd import synth
     cfg = dict(synth.ELLIPSOID_D2048, mm=mm, dtype=dtype, xo="nec")
     sampled_rows(cfg, gens=2, n_sample=6, rot=rotation(2048, 0))
+
+
+# ---- captured graphs replay the same generations ------------------------------
+
+@pytest.mark.parametrize("kind", ["nec", "rotated", "batched"])
+def test_graph_replay_matches_direct_launches(kind):
+    from paper_2101_06599_amd import synth
+    rot = None
+    if kind == "nec":
+        cfgs = [rast(N=64, D=300, xo="nec", dtype="fp64")]
+    elif kind == "rotated":
+        rot = rotation(96, 3)
+        cfgs = [ell("fp32", "fp32", D=96, N=40, xo="bin")]
+    else:
+        cfgs = synth.batch_table(n_runs=5, seed=2, max_D=200, max_N=40)
+    a, b = DE(cfgs, rot), DE(cfgs, rot)
+    b.graph(True)
+    for n in (5, 130, 64, 3, 70):
+        a.generation(n)
+        b.generation(n)
+    # resume from a checkpoint in both, then more replayed blocks
+    pop, fit, g = a.state(0)
+    fb, ib, gb, _ = a.best(0)
+    for h in (a, b):
+        h.set_state(0, pop, fit, g + 7, float(fit[ib]), ib, gb)
+        h.generation(150)
+    for r in range(len(cfgs)):
+        pa, fa, ga = a.state(r)
+        pb, fb2, gb2 = b.state(r)
+        assert ga == gb2
+        assert np.array_equal(pa, pb) and np.array_equal(fa, fb2)
+        assert a.best(r)[:3] == b.best(r)[:3]
+
+
+def test_autotuned_row_width_gives_same_generations():
+    from paper_2101_06599_amd.tune import tune_tpr
+    cfg = rast(N=48, D=700, xo="nec", dtype="fp32")
+    best, table = tune_tpr(cfg, gens=8, use_cache=False)
+    assert best in (64, 256, 512, 1024) and set(table) == {64, 256, 512, 1024}
+    assert all(v > 0 for v in table.values())
+    a, b = DE([cfg]), DE([dict(cfg, tpr=best)])
+    a.generation(20)
+    b.generation(20)
+    pa, fa, _ = a.state(0)
+    pb, fb, _ = b.state(0)
+    assert np.array_equal(pa, pb)
+    assert np.all(np.abs(fa - fb) <= 1e-5 * np.abs(fa))
