@@ -240,12 +240,14 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
 
   // Alg 2 lines 8-10 for this row: trial = parent with the masked elements
   // replaced by x_r0 + F (x_r1 - x_r2), evaluated on the fly.
-  // Phase 1 (64-lane rows): every cached chunk's parent (and shift) loads go
-  // out together; wide rows load each chunk as they reach it.
+  // Phase 1 (64-lane rows of one run): every cached chunk's parent (and
+  // shift) loads go out together; wide rows and batched launches, where
+  // occupancy matters more, load each chunk as they reach it.
+  constexpr bool kPrefetch = S::PREFETCH && !BATCH;
   constexpr bool kShift = FN == FN_RASTRIGIN || FN == FN_ROSENBROCK || FN == FN_ANY;
   const bool shifted = kShift && (FN != FN_ANY || fn != FN_SPHERE);
   V4<T> xs[MAXIT], os[MAXIT];
-  if constexpr (S::PREFETCH) {
+  if constexpr (kPrefetch) {
 #pragma unroll
     for (int k = 0; k < MAXIT; ++k) {
       const uint32_t c = k * TPR + t;
@@ -261,7 +263,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
     const uint32_t c = k * TPR + t;
     mb[k] = 0;
     if (c < nchunk) {
-      if constexpr (!S::PREFETCH) {
+      if constexpr (!kPrefetch) {
         xs[k] = load4(R.xi + 4 * c);
         if (shifted) os[k] = load4(R.o + 4 * c);
       }
