@@ -67,9 +67,9 @@ def compare_generation(gpu, ref, cfg, run=0, resync=True, rot=None, trace=None, 
     ri = rt["idx"]
     assert np.array_equal(gi[:, :5], ri[:, :5]), _first_diff(gi[:, :5], ri[:, :5], "indices/L")
     assert np.array_equal(gm, rt["mask"]), _first_diff(gm, rt["mask"], "mask")
-    assert np.array_equal(gt, rt["trial"]), _first_diff(gt, rt["trial"], "trial")
+    assert np.array_equal(gt, rt["trial"], equal_nan=True), _first_diff(gt, rt["trial"], "trial")
     phi_u = phi_rows(cfg, rt["trial"], o, rot)
-    err = np.abs(gf - rt["ftrial"])
+    err = fit_err(gf, rt["ftrial"])
     assert np.all(err <= tol * phi_u), f"trial fitness: max rel {np.max(err / phi_u):.3e}"
     win_g = gi[:, 5].astype(bool)
     win_r = ri[:, 5].astype(bool)
@@ -83,17 +83,25 @@ def compare_generation(gpu, ref, cfg, run=0, resync=True, rot=None, trace=None, 
     pop_r, fit_r, gr = ref.state()
     assert gg == gr == g0 + 1
     if flips.size == 0:
-        assert np.array_equal(pop_g.astype(np.float64), pop_r), "population differs"
+        assert np.array_equal(pop_g.astype(np.float64), pop_r, equal_nan=True), "population differs"
         phi_x = phi_rows(cfg, pop_r, o, rot)
-        assert np.all(np.abs(fit_g - fit_r) <= tol * phi_x)
+        assert np.all(fit_err(fit_g.astype(np.float64), fit_r) <= tol * phi_x)
     elif resync:
         bf, bi, bgen, _ = ref.best()
         gpu.set_state(run, pop_r, fit_r, gr, bf, bi, bgen)
     return int(flips.size)
 
 
+def fit_err(a, b):
+    """|a - b| with equal infinities (NaN fitness counts as +inf) at zero."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    same_inf = np.isinf(a) & np.isinf(b) & (np.sign(a) == np.sign(b))
+    return np.where(same_inf, 0.0, np.abs(a - b))
+
+
 def _first_diff(a, b, what):
-    idx = np.argwhere(a != b)
+    idx = np.argwhere((a != b) & ~(np.isnan(a) & np.isnan(b)))
     if idx.size == 0:
         return what
     k = tuple(idx[0])

@@ -353,3 +353,58 @@ def test_autotuned_row_width_gives_same_generations():
     pb, fb, _ = b.state(0)
     assert np.array_equal(pa, pb)
     assert np.all(np.abs(fa - fb) <= 1e-5 * np.abs(fa))
+
+
+# ---- edge cases --------------------------------------------------------------
+
+@pytest.mark.parametrize("xo,impl", [("bin", "lane"), ("exp", "scan"), ("exp", "job"),
+                                     ("nec", "lane")])
+@pytest.mark.parametrize("D", [1, 2])
+def test_minimum_population_and_dimension(xo, impl, D):
+    # N = 4: r0, r1, r2 are exactly the three other rows, in drawn order
+    cfg = c1(xo, N=4, D=D, exp_impl=impl)
+    gpu, ref, _ = run_parity(cfg, 30)
+    assert gpu.best(0)[1:3] == ref.best()[1:3]
+
+
+def test_large_population_tiny_dimension():
+    cfg = dict(N=1 << 20, D=4, F=0.7, CR=0.5, xo="bin", fn="rastrigin", dtype="fp32",
+               lo=-5.12, hi=5.12, olo=-4.0, ohi=4.0, seed=11)
+    sampled_rows(cfg, gens=2, n_sample=64)
+
+
+def test_huge_dimension_minimum_population():
+    # rows far beyond the register cache of 1024 lanes, ragged tail
+    cfg = dict(N=4, D=(1 << 20) - 3, F=0.5, CR=0.999, xo="nec", fn="rosenbrock",
+               dtype="fp32", lo=-5.12, hi=5.12, olo=-4.0, ohi=4.0, seed=12)
+    sampled_rows(cfg, gens=2, n_sample=4)
+
+
+def test_nan_rows_never_win():
+    cfg = rast(N=20, D=50, xo="bin", CR=1.0)
+    gpu = DE([cfg])
+    ref = oracle_run(cfg)
+    pop, fit, g = ref.state()
+    pop[3] = np.nan
+    fit[3] = np.inf
+    bf, bi, bg, _ = ref.best()
+    ref.set_state(pop, fit, g, bf, bi, bg)
+    gpu.set_state(0, pop, fit, g, bf, bi, bg)
+    trace = gpu.trace(0)
+    for _ in range(5):
+        compare_generation(gpu, ref, cfg, trace=trace)
+        t = trace["trial"].cpu().numpy()
+        win = trace["idx"].cpu().numpy()[:, 5].astype(bool)
+        assert not np.any(win & np.isnan(t).any(axis=1))
+        assert np.isinf(trace["ftrial"].cpu().numpy()[np.isnan(t).any(axis=1)]).all()
+
+
+def test_empty_calls():
+    import torch
+    gpu = DE([c1("nec")])
+    before = gpu.state(0)
+    gpu.generation(0)
+    out = gpu.evaluate(0, torch.zeros((0, 10), dtype=torch.float64, device="cuda:0"))
+    assert out.numel() == 0
+    after = gpu.state(0)
+    assert np.array_equal(before[0], after[0]) and before[2] == after[2] == 0
