@@ -149,6 +149,48 @@ def cpu_baseline(cfg, seconds=15.0):
                       f"{dt:.1f} s"}
 
 
+# Table 1 of the paper: total time (presumably seconds) of mask generation over
+# Cr in {0.2, 0.4, 0.6, 0.8, 1.0} x 100 repeats, CuPy on a GTX 760:
+# (D, Np) -> (CUDA-nec, CUDA-bin).
+PAPER_TABLE1 = {(10, 100): (1.76, 6.99), (10, 1000): (1.18, 0.64), (10, 10000): (1.34, 0.94),
+                (100, 100): (1.16, 0.66), (100, 1000): (1.23, 0.64), (100, 10000): (1.11, 1.36),
+                (1000, 100): (0.66, 0.56), (1000, 1000): (1.07, 1.00), (1000, 10000): (4.31, 4.56),
+                (10000, 100): (1.48, 0.97), (10000, 1000): (4.43, 3.91),
+                (10000, 10000): (33.26, 39.14)}
+
+
+def table1(torch, de, reps=100):
+    """The paper's crossover-only grid: masks of 100 generations per Cr, summed
+    over the five Cr values, with the masks written to device memory."""
+    res = {}
+    for (D, N), (p_nec, p_bin) in PAPER_TABLE1.items():
+        row = {}
+        for xo, paper in (("nec", p_nec), ("bin", p_bin), ("exp", None)):
+            total = 0.0
+            for CR in (0.2, 0.4, 0.6, 0.8, 1.0):
+                h = de.DE([dict(N=N, D=D, CR=CR, xo=xo, exp_impl="scan", fn="sphere",
+                                dtype="fp32", seed=0)])
+                out = torch.empty((N, D), dtype=torch.uint8, device="cuda:0")
+                h.masks(0, 1, out)
+                s = torch.cuda.current_stream()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record(s)
+                for g in range(1, reps + 1):
+                    h.masks(0, g, out)
+                e1.record(s)
+                torch.cuda.synchronize()
+                total += e0.elapsed_time(e1) / 1e3
+                h.close()
+                del out
+            row[xo] = {"total_s": total}
+            if paper is not None:
+                row[xo].update(paper_cuda_s=paper, speedup_vs_paper=paper / total)
+        res[f"D{D}_N{N}"] = row
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,7 +198,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections", default="all",
                     help="comma list of: head (headline only), variants, rosenbrock, rotated, "
-                         "batched, tuning, cpu, copy (default: all but copy)")
+                         "batched, table1, tuning, cpu, copy (default: all but copy)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -170,7 +212,7 @@ def main():
     torch.cuda.set_device(0)
     de.lib()
     secs = set(args.sections.split(",")) if args.sections != "all" else {
-        "variants", "rosenbrock", "rotated", "batched", "tuning", "cpu"}
+        "variants", "rosenbrock", "rotated", "batched", "table1", "tuning", "cpu"}
     K, W = args.steps, args.warmup
 
     head = dict(synth.RASTRIGIN_D1000, xo="nec", dtype="fp64")
@@ -265,6 +307,9 @@ def main():
             "pop_dim_gen_s": elems * kb / (ms / 1e3),
             "hbm_frac_kernel": byt / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         g2.close()
+
+    if "table1" in secs:
+        out["table1_masks"] = table1(torch, de)
 
     if "tuning" in secs:
         from paper_2101_06599_amd.tune import tune_tpr

@@ -149,6 +149,14 @@ de_status de_set_state(de_handle* h, int32_t run, const void* pop_host, const vo
                        int64_t gen, double best_f, int64_t best_idx, int64_t best_gen,
                        void* stream);
 
+/* The crossover masks of generation `gen` (>= 1, the run's own generation
+ * number) of one run, exactly as that generation applies them: the N x D
+ * 0/1 matrix that Alg 7 (binomial) and Alg 10 (NEC) return, or the run of
+ * Alg 8 (classic exponential), one byte per element, row-major, written to
+ * the device buffer `mask` (N * D bytes, caller-owned).  Does not change the
+ * run's state.  Asynchronous. */
+de_status de_masks(de_handle* h, int32_t run, int64_t gen, uint8_t* mask, void* stream);
+
 /* Debug trace of one run, written by the production kernels for every later
  * generation (each overwrites the previous one).  All device pointers, each
  * may be NULL; all NULL switches tracing off.

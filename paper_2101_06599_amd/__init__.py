@@ -25,7 +25,7 @@ MM = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 
 ABI_FUNCTIONS = ("de_workspace_size", "de_init", "de_generation", "de_evaluate", "de_best",
                  "de_get_state", "de_set_state", "de_trace", "de_profile", "de_profile_read",
-                 "de_graph", "de_last_error", "de_destroy")
+                 "de_graph", "de_masks", "de_last_error", "de_destroy")
 
 
 class DEError(RuntimeError):
@@ -66,6 +66,7 @@ def lib():
         L.de_profile.argtypes = [vp, i32]
         L.de_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
         L.de_graph.argtypes = [vp, i32]
+        L.de_masks.argtypes = [vp, i32, i64, vp, vp]
         L.de_last_error.argtypes = [vp]
         L.de_last_error.restype = C.c_char_p
         L.de_destroy.argtypes = [vp]
@@ -216,6 +217,16 @@ class DE:
         n = C.c_int64(0)
         self._check(lib().de_profile_read(self._h, C.byref(ms), C.byref(n)), self._h)
         return ms.value, n.value
+
+    def masks(self, run: int, gen: int, out=None):
+        """Crossover masks of generation `gen` of a run (N x D uint8 device tensor)."""
+        t = self.torch
+        N, D = int(self.runs[run]["N"]), int(self.runs[run]["D"])
+        if out is None:
+            out = t.empty((N, D), dtype=t.uint8, device=self.device)
+        self._check(lib().de_masks(self._h, run, int(gen), C.c_void_p(out.data_ptr()), _stream()),
+                    self._h)
+        return out
 
     def graph(self, enable: bool = True):
         """Replay captured 64-generation graphs in generation() (same results)."""

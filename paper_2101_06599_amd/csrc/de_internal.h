@@ -116,6 +116,9 @@ hipError_t launch_best_fp64(const RunDev* runs, const RunDev& h, int run, uint32
 hipError_t launch_normalize(const RunDev* runs, const RunDev& h, int run, uint32_t gcur,
                             hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
+// crossover masks of generation g (run generation number), N x D bytes
+hipError_t launch_masks(const RunDev* runs, const RunDev& h, int run, uint32_t g, uint8_t* out,
+                        hipStream_t s);
 // rotated function: M pieces and weights from the caller's FP64 M; fitness of
 // N rows (the trials of the coming generation when `trials`, else the
 // population) into fit_dst or, when select, straight into greedy selection.

@@ -626,6 +626,16 @@ de_status de_set_state(de_handle* h, int32_t run, const void* pop_host, const vo
   return DE_OK;
 }
 
+de_status de_masks(de_handle* h, int32_t run, int64_t gen, uint8_t* mask, void* stream) {
+  de_status st = check_run(h, run);
+  if (st != DE_OK) return st;
+  if (gen < 1 || gen >= 0xFFFFFFFFll) return fail(h, DE_E_INVALID, "gen must be in [1, 2^32 - 1)");
+  if (!mask) return fail(h, DE_E_INVALID, "mask is NULL");
+  HIPCHECK(h, de::launch_masks(h->dev_runs, h->host[run], run, static_cast<uint32_t>(gen), mask,
+                               static_cast<hipStream_t>(stream)));
+  return DE_OK;
+}
+
 de_status de_trace(de_handle* h, int32_t run, int64_t* idx, uint8_t* mask, void* trial,
                    void* ftrial) {
   de_status st = check_run(h, run);

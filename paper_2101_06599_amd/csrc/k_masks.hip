@@ -1,0 +1,68 @@
+// Crossover masks on their own: for generation g of a run, the N x D 0/1
+// matrix of Alg 7 (binomial), Alg 8 (classic exponential) or Eq 9 + Alg 10
+// (NEC) that the generation kernel applies, written row-major as bytes.
+// One wavefront per individual; the draws are the generation kernel's.
+#include "de_device.h"
+
+namespace de {
+
+template <int XO>
+__global__ void __launch_bounds__(256) k_masks(const RunDev* __restrict__ runs, int32_t run,
+                                               uint32_t g, uint8_t* __restrict__ out) {
+  const RunDev& P = runs[run];
+  const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
+  const uint32_t row = blockIdx.x * 4 + threadIdx.x / 64;
+  if (row >= N) return;  // rows are whole wavefronts: a wavefront leaves together
+  const uint32_t i = __builtin_amdgcn_readfirstlane(row);
+  const uint32_t lane = threadIdx.x % 64;
+  const uint4 bx = draw(P, TAG_XO, g, i, 0);
+  const uint32_t jr = scale_index(bx.x, D);
+  uint32_t L = 0;
+  if constexpr (XO == XO_NEC) L = nec_length(P, bx.y);
+  if constexpr (XO == XO_EXP)
+    L = P.exp_impl == EXPI_SCAN ? exp_length_scan(P, g, i) : exp_length_serial(P, g, i);
+  const int64_t base = static_cast<int64_t>(i) * D;
+  DE_GLOBAL uint8_t* o = gmut<uint8_t>(out) + base;
+  const bool word_aligned = (base & 3) == 0;
+  for (uint32_t c = lane; 4 * c < D; c += 64) {
+    const uint32_t j0 = 4 * c;
+    uint32_t m = 0;
+    if constexpr (XO == XO_BIN) {
+      const uint4 b = draw(P, TAG_BIN, g, i, c);
+      m = (static_cast<uint64_t>(b.x) < P.thr ? 1u : 0u) |
+          (static_cast<uint64_t>(b.y) < P.thr ? 2u : 0u) |
+          (static_cast<uint64_t>(b.z) < P.thr ? 4u : 0u) |
+          (static_cast<uint64_t>(b.w) < P.thr ? 8u : 0u);
+      if (jr >= j0 && jr < j0 + 4) m |= 1u << (jr - j0);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t j = j0 + v;
+        const uint32_t off = j >= jr ? j - jr : j + D - jr;
+        m |= (off < L ? 1u : 0u) << v;
+      }
+    }
+    const uint32_t bytes = (m & 1u) | ((m & 2u) << 7) | ((m & 4u) << 14) | ((m & 8u) << 21);
+    if (word_aligned && j0 + 4 <= D) {
+      *(DE_GLOBAL uint32_t*)(o + j0) = bytes;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (j0 + v < D) o[j0 + v] = static_cast<uint8_t>((m >> v) & 1u);
+    }
+  }
+}
+
+hipError_t launch_masks(const RunDev* runs, const RunDev& h, int run, uint32_t g, uint8_t* out,
+                        hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>((h.N + 3) / 4);
+  switch (h.xo) {
+    case XO_BIN: hipLaunchKernelGGL(k_masks<XO_BIN>, dim3(blocks), dim3(256), 0, s, runs, run, g, out); break;
+    case XO_EXP: hipLaunchKernelGGL(k_masks<XO_EXP>, dim3(blocks), dim3(256), 0, s, runs, run, g, out); break;
+    case XO_NEC: hipLaunchKernelGGL(k_masks<XO_NEC>, dim3(blocks), dim3(256), 0, s, runs, run, g, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace de

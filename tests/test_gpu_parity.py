@@ -408,3 +408,43 @@ def test_empty_calls():
     assert out.numel() == 0
     after = gpu.state(0)
     assert np.array_equal(before[0], after[0]) and before[2] == after[2] == 0
+
+
+# ---- crossover masks on their own -----------------------------------------------
+
+def oracle_mask(seed, D, CR, xo, g, i):
+    jr = oracle.randint(oracle.word(seed, 0, "xo", g, i, 0, 0), D)
+    if xo == "bin":
+        return oracle.mask_bin(seed, 0, D, CR, g, i, jr)
+    if xo == "exp":
+        L = oracle.exp_length(seed, 0, D, CR, g, i)
+    else:
+        L = oracle.nec_length(oracle.uniform(oracle.word(seed, 0, "xo", g, i, 0, 1)), CR, D)
+    return oracle.alg9_mask(D, jr, L)
+
+
+@pytest.mark.parametrize("xo,impl", [("bin", "lane"), ("exp", "scan"), ("exp", "lane"),
+                                     ("nec", "lane")])
+@pytest.mark.parametrize("D,N,CR", [(10, 100, 0.2), (13, 37, 0.6), (1000, 64, 0.8),
+                                    (100, 30, 1.0), (257, 20, 0.0), (1, 5, 0.5)])
+def test_masks_match_oracle(xo, impl, D, N, CR):
+    cfg = dict(N=N, D=D, CR=CR, xo=xo, exp_impl=impl, fn="sphere", dtype="fp32", seed=9)
+    gpu = DE([cfg])
+    for g in (1, 2, 77):
+        m = gpu.masks(0, g).cpu().numpy()
+        for i in range(N):
+            assert np.array_equal(m[i], oracle_mask(9, D, CR, xo, g, i)), (g, i)
+    # the same masks the first generation applies
+    tr = gpu.trace(0)
+    m1 = gpu.masks(0, 1).cpu().numpy()
+    gpu.generation(1)
+    assert np.array_equal(tr["mask"].cpu().numpy(), m1)
+
+
+@pytest.mark.parametrize("xo", ["nec", "bin"])
+def test_masks_full_size_10000x10000(xo):
+    N = D = 10000
+    gpu = DE([dict(N=N, D=D, CR=0.6, xo=xo, fn="sphere", dtype="fp32", seed=0)])
+    m = gpu.masks(0, 5)
+    for i in np.random.default_rng(1).choice(N, 16, replace=False):
+        assert np.array_equal(m[int(i)].cpu().numpy(), oracle_mask(0, D, 0.6, xo, 5, int(i)))
