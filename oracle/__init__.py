@@ -19,7 +19,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 XO = {"bin": 0, "exp": 1, "nec": 2}
-FN = {"sphere": 0, "rastrigin": 1, "rosenbrock": 2, "ellipsoid_rot": 3}
+FN = {"sphere": 0, "rastrigin": 1, "rosenbrock": 2, "ellipsoid_rot": 3, "ackley": 4,
+      "griewank": 5}
 DTYPE = {"fp64": 0, "fp32": 1}
 TAG = {"init": 1, "shift": 2, "idx": 3, "xo": 4, "bin": 5, "exp": 6}
 

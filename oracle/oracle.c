@@ -203,6 +203,27 @@ double oracle_fitness(int fn, int64_t D, const double* x, const double* o, const
         s += 100.0L * a * a + b * b;
       }
       break;
+    case OR_FN_ACKLEY: {
+      /* Sec. 4, as printed: -20 exp(-0.02 sqrt(mean x^2)) - exp(mean cos 2 pi x) + 20 + e */
+      long double sq = 0.0L, cs = 0.0L;
+      for (int64_t j = 0; j < D; ++j) {
+        sq += (long double)x[j] * (long double)x[j];
+        cs += cosl(2.0L * PI_L * (long double)x[j]);
+      }
+      s = -20.0L * expl(-0.02L * sqrtl(sq / (long double)D)) - expl(cs / (long double)D) + 20.0L +
+          expl(1.0L);
+      break;
+    }
+    case OR_FN_GRIEWANK: {
+      /* Sec. 4: sum x_j^2 / 4000 - prod cos(x_j / sqrt(j)) + 1, j from 1 */
+      long double sq = 0.0L, pr = 1.0L;
+      for (int64_t j = 0; j < D; ++j) {
+        sq += (long double)x[j] * (long double)x[j];
+        pr *= cosl((long double)x[j] / sqrtl((long double)(j + 1)));
+      }
+      s = sq / 4000.0L - pr + 1.0L;
+      break;
+    }
     case OR_FN_ELLIPSOID_ROT:
       /* z = M (x - o); sum_k w_k z_k^2 */
       for (int64_t k = 0; k < D; ++k) {
@@ -220,6 +241,20 @@ double oracle_fitness(int fn, int64_t D, const double* x, const double* o, const
 
 double oracle_fitness_phi(int fn, int64_t D, const double* x, const double* o, const double* rot,
                           const double* w) {
+  if (fn == OR_FN_ACKLEY || fn == OR_FN_GRIEWANK) {
+    /* the final combination cancels near the optimum: scale by its parts */
+    long double sq = 0.0L, cs = 0.0L, pr = 1.0L;
+    for (int64_t j = 0; j < D; ++j) {
+      sq += (long double)x[j] * (long double)x[j];
+      if (fn == OR_FN_ACKLEY) cs += cosl(2.0L * PI_L * (long double)x[j]);
+      else pr *= cosl((long double)x[j] / sqrtl((long double)(j + 1)));
+    }
+    long double v = fn == OR_FN_ACKLEY
+                        ? 20.0L * expl(-0.02L * sqrtl(sq / (long double)D)) +
+                              expl(cs / (long double)D) + 20.0L + expl(1.0L)
+                        : sq / 4000.0L + fabsl(pr) + 1.0L;
+    return finite_or_inf(v);
+  }
   if (fn != OR_FN_ROSENBROCK) return oracle_fitness(fn, D, x, o, rot, w);
   long double s = 0.0L;
   for (int64_t j = 0; j + 1 < D; ++j) {
@@ -251,7 +286,9 @@ struct oracle_state {
   int64_t best_idx, best_gen;
 };
 
-static int uses_shift(int fn) { return fn != OR_FN_SPHERE; }
+static int uses_shift(int fn) {
+  return fn == OR_FN_RASTRIGIN || fn == OR_FN_ROSENBROCK || fn == OR_FN_ELLIPSOID_ROT;
+}
 
 /* Uniform sample in [lo, hi] for element j: FP64 takes 53 bits from two
  * words of block j/2, FP32 takes 24 bits from word j%4 of block j/4. */

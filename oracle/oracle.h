@@ -31,7 +31,8 @@ extern "C" {
 #endif
 
 enum { OR_XO_BIN = 0, OR_XO_EXP = 1, OR_XO_NEC = 2 };
-enum { OR_FN_SPHERE = 0, OR_FN_RASTRIGIN = 1, OR_FN_ROSENBROCK = 2, OR_FN_ELLIPSOID_ROT = 3 };
+enum { OR_FN_SPHERE = 0, OR_FN_RASTRIGIN = 1, OR_FN_ROSENBROCK = 2, OR_FN_ELLIPSOID_ROT = 3,
+       OR_FN_ACKLEY = 4, OR_FN_GRIEWANK = 5 };
 enum { OR_FP64 = 0, OR_FP32 = 1 };
 enum { OR_TAG_INIT = 1, OR_TAG_SHIFT = 2, OR_TAG_IDX = 3, OR_TAG_XO = 4, OR_TAG_BIN = 5, OR_TAG_EXP = 6 };
 

@@ -96,3 +96,28 @@ def test_nan_is_plus_infinity():
     assert oracle.fitness("sphere", x) == math.inf
     assert oracle.fitness("rastrigin", x, np.zeros(3)) == math.inf
     assert oracle.fitness("rosenbrock", x, np.zeros(3)) == math.inf
+
+
+@pytest.mark.parametrize("D", [1, 10, 1000])
+def test_ackley_optimum_and_integer_points(D):
+    assert abs(oracle.fitness("ackley", np.zeros(D))) <= 1e-15
+    for c in (1.0, -3.0, 7.0):
+        # cos(2 pi c) = 1 at integers, so f = 20 (1 - exp(-0.02 |c|))
+        ref = 20.0 * (1.0 - math.exp(-0.02 * abs(c)))
+        assert abs(oracle.fitness("ackley", np.full(D, c)) - ref) <= 1e-14 * ref
+    half = np.full(D, 0.5)  # cos(pi) = -1: f = 20 (1 - exp(-0.01)) + e - 1/e
+    ref = 20.0 * (1.0 - math.exp(-0.01)) + math.e - 1.0 / math.e
+    assert abs(oracle.fitness("ackley", half) - ref) <= 1e-14 * ref
+
+
+@pytest.mark.parametrize("D", [1, 2, 10, 500])
+def test_griewank_optimum_and_cosine_points(D):
+    j = np.arange(1, D + 1, dtype=np.float64)
+    assert oracle.fitness("griewank", np.zeros(D)) == 0.0
+    x = 2.0 * np.pi * np.sqrt(j)      # every cosine is +1
+    ref = float(np.sum(x * x)) / 4000.0
+    assert abs(oracle.fitness("griewank", x) - ref) <= 1e-13 * ref
+    y = np.pi * np.sqrt(j)            # every cosine is -1
+    ref = float(np.sum(y * y)) / 4000.0 + 1.0 - (-1.0) ** D
+    assert abs(oracle.fitness("griewank", y) - ref) <= 1e-13 * ref
+    assert oracle.fitness_phi("griewank", y) >= oracle.fitness("griewank", y)
