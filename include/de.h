@@ -70,12 +70,19 @@ typedef enum { DE_EXP_LANE = 0, DE_EXP_JOB = 1, DE_EXP_SCAN = 2 } de_exp_impl;
  *   SPHERE:        sum x_j^2
  *   RASTRIGIN:     sum z_j^2 - 10 cos(2 pi z_j) + 10
  *   ROSENBROCK:    sum_{j<D-1} 100 (z_{j+1} - z_j^2)^2 + (z_j - 1)^2 with z = x - o + 1
- *   ELLIPSOID_ROT: sum_k 10^(6k/(D-1)) (M (x - o))_k^2, M a caller-supplied D x D matrix */
+ *   ELLIPSOID_ROT: sum_k 10^(6k/(D-1)) (M (x - o))_k^2, M a caller-supplied D x D matrix
+ *   ACKLEY:        -20 exp(-0.02 sqrt(mean x_j^2)) - exp(mean cos(2 pi x_j)) + 20 + e
+ *                  (Sec. 4, with its 0.02; not shifted)
+ *   GRIEWANK:      sum x_j^2 / 4000 - prod_j cos(x_j / sqrt(j)) + 1, j counted from 1
+ *                  (Sec. 4; not shifted)
+ * ACKLEY and GRIEWANK run as single runs only (not in batched handles). */
 typedef enum {
   DE_FN_SPHERE = 0,
   DE_FN_RASTRIGIN = 1,
   DE_FN_ROSENBROCK = 2,
-  DE_FN_ELLIPSOID_ROT = 3
+  DE_FN_ELLIPSOID_ROT = 3,
+  DE_FN_ACKLEY = 4,
+  DE_FN_GRIEWANK = 5
 } de_function;
 
 typedef enum { DE_FP64 = 0, DE_FP32 = 1 } de_dtype;
@@ -99,11 +106,13 @@ typedef struct {
   int32_t exp_impl; /* de_exp_impl, DE_XO_EXP only */
   int32_t tpr;      /* lanes per individual in the generation kernel: 0 = chosen
                        from D; 64, 256, 512 or 1024 forces it (batched: 0 or 64).
-                       Results do not depend on it. */
+                       Indices, masks and trial rows do not depend on it;
+                       fitness sums only change their rounding order. */
   double lo, hi;    /* initial population drawn uniformly from [lo, hi]^D, lo < hi */
   double olo, ohi;  /* shift o drawn uniformly from [olo, ohi]^D when shift == NULL */
   uint64_t seed;    /* Philox key */
-  const void* shift;  /* device, D values of dtype, or NULL (not read for SPHERE) */
+  const void* shift;  /* device, D values of dtype, or NULL (not read for SPHERE,
+                         ACKLEY, GRIEWANK) */
   const double* rot;  /* device, D x D row-major FP64 M (ELLIPSOID_ROT only, else NULL) */
 } de_run_desc;
 

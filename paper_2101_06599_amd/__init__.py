@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libde.so")
 OK, E_INVALID, E_UNSUPPORTED, E_HIP, E_WORKSPACE, E_STATE = range(6)
 XO = {"bin": 0, "exp": 1, "nec": 2}
 EXP_IMPL = {"lane": 0, "job": 1, "scan": 2}
-FN = {"sphere": 0, "rastrigin": 1, "rosenbrock": 2, "ellipsoid_rot": 3}
+FN = {"sphere": 0, "rastrigin": 1, "rosenbrock": 2, "ellipsoid_rot": 3, "ackley": 4, "griewank": 5}
 DTYPE = {"fp64": 0, "fp32": 1}
 MM = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 

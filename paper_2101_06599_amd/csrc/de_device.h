@@ -151,6 +151,9 @@ template <> struct Math<double> {
     return __builtin_fma(a, b, c);
   }
   static __device__ __forceinline__ double sinpi_(double x) { return sinpi(x); }
+  static __device__ __forceinline__ double cos_(double x) { return cos(x); }
+  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
   static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
 };
 template <> struct Math<float> {
@@ -158,6 +161,9 @@ template <> struct Math<float> {
     return __builtin_fmaf(a, b, c);
   }
   static __device__ __forceinline__ float sinpi_(float x) { return sinpif(x); }
+  static __device__ __forceinline__ float cos_(float x) { return cosf(x); }
+  static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
+  static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
   static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
 };
 
@@ -180,6 +186,65 @@ __device__ __forceinline__ T rosen_term(T z0, T z1) {
   const T a = z1 - z0 * z0;
   const T b = z0 - T(1);
   return Math<T>::fma_(T(100) * a, a, b * b);
+}
+
+// Ackley and Griewank (Sec. 4) need two row statistics: s1 = sum x_j^2 and a
+// second one, s2, combined once the row is reduced.
+//   Ackley:   s2 = sum sin^2(pi x_j), since mean cos(2 pi x) = 1 - 2 s2 / D; then
+//             f = -20 expm1(-0.02 sqrt(s1 / D)) - e expm1(-2 s2 / D), the same
+//             value as the printed form without its cancellation near x = 0.
+//   Griewank: s2 = prod cos(x_j / sqrt(j)) (j from 1); f = (1 - s2) + s1 / 4000.
+template <int FN> constexpr bool kTwoStat = FN == FN_ACKLEY || FN == FN_GRIEWANK;
+
+template <typename T, int FN>
+__device__ __forceinline__ T stat2_init() {
+  return FN == FN_GRIEWANK ? T(1) : T(0);
+}
+
+// Element j's part of s2 (j counted from 0).
+template <typename T, int FN>
+__device__ __forceinline__ T stat2_term(T x, uint32_t j) {
+  if constexpr (FN == FN_ACKLEY) {
+    const T s = Math<T>::sinpi_(x);
+    return s * s;
+  } else {
+    return Math<T>::cos_(x / Math<T>::sqrt_(static_cast<T>(j + 1)));
+  }
+}
+
+template <typename T, int FN>
+__device__ __forceinline__ T stat2_join(T a, T b) {
+  return FN == FN_GRIEWANK ? a * b : a + b;
+}
+
+template <typename T, int FN>
+__device__ __forceinline__ T stat2_finish(T s1, T s2, uint32_t D) {
+  if constexpr (FN == FN_ACKLEY) {
+    const T d = static_cast<T>(D);
+    const T r = Math<T>::sqrt_(s1 / d);
+    return T(-20) * Math<T>::expm1_(T(-0.02) * r) -
+           T(2.718281828459045235360287) * Math<T>::expm1_(T(-2) * s2 / d);
+  } else {
+    return (T(1) - s2) + s1 / T(4000);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_prod(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v *= __shfl_xor(v, off);
+  return v;
+}
+
+template <typename T, int FN>
+__device__ __forceinline__ T wave_stat2(T v) {
+  if constexpr (FN == FN_GRIEWANK) {
+    return wave_prod(v);
+  } else {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+  }
 }
 
 template <typename T>

@@ -8,8 +8,8 @@
 
 namespace de {
 
-enum : int { FN_SPHERE = 0, FN_RASTRIGIN = 1, FN_ROSENBROCK = 2, FN_ELLIPSOID = 3, FN_ANY = -1,
-             FN_NONE = -2 };
+enum : int { FN_SPHERE = 0, FN_RASTRIGIN = 1, FN_ROSENBROCK = 2, FN_ELLIPSOID = 3, FN_ACKLEY = 4,
+             FN_GRIEWANK = 5, FN_ANY = -1, FN_NONE = -2 };
 enum : int { XO_BIN = 0, XO_EXP = 1, XO_NEC = 2, XO_ANY = -1 };
 enum : int { EXPI_LANE = 0, EXPI_JOB = 1, EXPI_SCAN = 2 };
 enum : uint32_t { TAG_INIT = 1, TAG_SHIFT = 2, TAG_IDX = 3, TAG_XO = 4, TAG_BIN = 5, TAG_EXP = 6 };

@@ -102,6 +102,11 @@ size_t bump(size_t& cur, size_t bytes) {
   return at;
 }
 
+// Functions evaluated at z = x - o (the others never read a shift).
+bool is_shifted(int fn) {
+  return fn == DE_FN_RASTRIGIN || fn == DE_FN_ROSENBROCK || fn == DE_FN_ELLIPSOID_ROT;
+}
+
 de_status validate(const de_run_desc* runs, int32_t n_runs, std::string& msg) {
   if (!runs || n_runs < 1) { msg = "runs must be a non-empty array"; return DE_E_INVALID; }
   for (int r = 0; r < n_runs; ++r) {
@@ -119,12 +124,12 @@ de_status validate(const de_run_desc* runs, int32_t n_runs, std::string& msg) {
     if (!(std::isfinite(d.lo) && std::isfinite(d.hi) && d.lo < d.hi)) return bad("need finite lo < hi");
     if (d.dtype != DE_FP64 && d.dtype != DE_FP32) return bad("unknown dtype");
     if (d.xo < DE_XO_BIN || d.xo > DE_XO_NEC) return bad("unknown crossover");
-    if (d.fn < DE_FN_SPHERE || d.fn > DE_FN_ELLIPSOID_ROT) return bad("unknown function");
+    if (d.fn < DE_FN_SPHERE || d.fn > DE_FN_GRIEWANK) return bad("unknown function");
     if (d.exp_impl < DE_EXP_LANE || d.exp_impl > DE_EXP_SCAN) return bad("unknown exp_impl");
     if (d.tpr != 0 && d.tpr != 64 && d.tpr != 256 && d.tpr != 512 && d.tpr != 1024)
       return bad("tpr must be 0, 64, 256, 512 or 1024");
     if (n_runs > 1 && d.tpr != 0 && d.tpr != 64) return bad("batched runs use tpr 0 or 64");
-    if (d.fn != DE_FN_SPHERE && !d.shift &&
+    if (is_shifted(d.fn) && !d.shift &&
         !(std::isfinite(d.olo) && std::isfinite(d.ohi) && d.olo <= d.ohi))
       return bad("need finite olo <= ohi when shift is NULL");
     if (d.fn == DE_FN_ELLIPSOID_ROT) {
@@ -141,9 +146,10 @@ de_status validate(const de_run_desc* runs, int32_t n_runs, std::string& msg) {
       }
     }
     if (n_runs > 1) {
-      if (d.fn == DE_FN_ELLIPSOID_ROT || (d.xo == DE_XO_EXP && d.exp_impl == DE_EXP_JOB)) {
+      if (d.fn == DE_FN_ELLIPSOID_ROT || d.fn == DE_FN_ACKLEY || d.fn == DE_FN_GRIEWANK ||
+          (d.xo == DE_XO_EXP && d.exp_impl == DE_EXP_JOB)) {
         std::snprintf(buf, sizeof buf,
-                      "run %d: batched launches support the separable functions and the "
+                      "run %d: batched launches support sphere, Rastrigin and Rosenbrock and the "
                       "lane/scan exponential crossover only", r);
         msg = buf;
         return DE_E_UNSUPPORTED;
@@ -452,7 +458,7 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
     HIPINIT(hipMemcpyAsync(const_cast<uint64_t*>(R.T), h->tables[r].data(),
                            sizeof(uint64_t) * (d.D + 2), hipMemcpyHostToDevice, s));
     HIPINIT(de::launch_init_impl(h->dev_runs, R, r, d.lo, d.hi, d.olo, d.ohi,
-                                 d.fn == DE_FN_SPHERE ? nullptr : d.shift, s));
+                                 is_shifted(d.fn) ? d.shift : nullptr, s));
     if (d.fn == DE_FN_ELLIPSOID_ROT) {
       HIPINIT(de::launch_prepare_rot(R, s));
       HIPINIT(de::launch_rot_init_fit(h->dev_runs, R, r, s));

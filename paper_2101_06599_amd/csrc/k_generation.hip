@@ -118,10 +118,10 @@ __device__ __forceinline__ T chunk_terms(const RowCtx<T>& R, uint32_t c, const T
                                          const V4<T>& o, T& zfirst) {
   const uint32_t j0 = 4 * c;
   T acc = T(0);
-  if constexpr (FN == FN_SPHERE) {
+  if constexpr (FN == FN_SPHERE || kTwoStat<FN>) {
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      if (j0 + v < R.D) acc += point_term<T, FN>(u[v], T(0));
+      if (j0 + v < R.D) acc += point_term<T, FN_SPHERE>(u[v], T(0));
   } else if constexpr (FN == FN_RASTRIGIN) {
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -136,6 +136,17 @@ __device__ __forceinline__ T chunk_terms(const RowCtx<T>& R, uint32_t c, const T
     zfirst = z[0];
   }
   return acc;
+}
+
+// The second row statistic of Ackley and Griewank over one chunk.
+template <typename T, int FN>
+__device__ __forceinline__ void chunk_stat2(const RowCtx<T>& R, uint32_t c, const T (&u)[4], T& s2) {
+  if constexpr (kTwoStat<FN>) {
+    const uint32_t j0 = 4 * c;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (j0 + v < R.D) s2 = stat2_join<T, FN>(s2, stat2_term<T, FN>(u[v], j0 + v));
+  }
 }
 
 template <typename T>
@@ -169,6 +180,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   using S = Shape<TPR>;
   __shared__ T red[S::RPB * S::NW];
   __shared__ uint32_t redc[S::RPB * S::NW];
+  __shared__ T red2[kTwoStat<FN> ? S::RPB * S::NW : 1];
   __shared__ T zsh[(FN == FN_ROSENBROCK || FN == FN_ANY) ? S::RPB * TPR * MAXIT + 1 : 1];
 
   const uint32_t t = threadIdx.x % TPR;
@@ -235,6 +247,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   T u[MAXIT][4];
   uint32_t mb[MAXIT];
   T acc = T(0);
+  T acc2 = stat2_init<T, FN>();  // Ackley / Griewank only
   uint32_t cnt = 0;
   T* zrow = zsh + slot * (TPR * MAXIT);
 
@@ -273,6 +286,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
         T zf = T(0);
         acc += FN == FN_ANY ? runtime_terms(fn, R, c, u[k], os[k], zf)
                             : chunk_terms<T, FN>(R, c, u[k], os[k], zf);
+        chunk_stat2<T, FN>(R, c, u[k], acc2);
         if constexpr (FN == FN_ROSENBROCK || FN == FN_ANY) zrow[c] = zf;
       }
     }
@@ -288,6 +302,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
       if (kShift && (FN != FN_ANY || fn != FN_SPHERE)) ov = load4(R.o + 4 * c);
       acc += FN == FN_ANY ? runtime_terms(fn, R, c, v, ov, zf)
                           : chunk_terms<T, FN>(R, c, v, ov, zf);
+      chunk_stat2<T, FN>(R, c, v, acc2);
       if ((FN == FN_ROSENBROCK || (FN == FN_ANY && fn == FN_ROSENBROCK)) && 4 * c + 4 < R.D) {
         const T zn = (trial_elem(P, R, 4 * c + 4) - R.o[4 * c + 4]) + T(1);
         const T zl = (v[3] - R.o[4 * c + 3]) + T(1);
@@ -319,24 +334,31 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
 
   // Row reduction in a fixed order (wave butterfly, then waves in order).
   T tot = wave_sum(acc);
+  T tot2 = T(0);
+  if constexpr (kTwoStat<FN>) tot2 = wave_stat2<T, FN>(acc2);
   uint32_t ctot = tracing ? static_cast<uint32_t>(wave_sum(static_cast<int>(cnt))) : 0u;
   if constexpr (S::NW > 1) {
     if (lane == 0) {
       red[slot * S::NW + wave] = tot;
       redc[slot * S::NW + wave] = ctot;
+      if constexpr (kTwoStat<FN>) red2[slot * S::NW + wave] = tot2;
     }
     __syncthreads();
     tot = T(0);
     ctot = 0;
+    if constexpr (kTwoStat<FN>) tot2 = stat2_init<T, FN>();
 #pragma unroll
     for (int w = 0; w < S::NW; ++w) {
       tot += red[slot * S::NW + w];
       ctot += redc[slot * S::NW + w];
+      if constexpr (kTwoStat<FN>) tot2 = stat2_join<T, FN>(tot2, red2[slot * S::NW + w]);
     }
   }
 
   if (!live) return;
-  const T fu = canon(tot);
+  T fraw = tot;
+  if constexpr (kTwoStat<FN>) fraw = stat2_finish<T, FN>(tot, tot2, R.D);
+  const T fu = canon(fraw);
   bool win = true;
   if constexpr (FN != FN_NONE) {
     // Alg 1 line 10 / Alg 2 line 11: strictly lower fitness replaces.
@@ -432,6 +454,8 @@ static hipError_t go_fn(const GenLaunch& L, int fn, int xo, bool batched) {
     case FN_SPHERE: return go_xo<T, FN_SPHERE>(L, xo, false);
     case FN_RASTRIGIN: return go_xo<T, FN_RASTRIGIN>(L, xo, false);
     case FN_ROSENBROCK: return go_xo<T, FN_ROSENBROCK>(L, xo, false);
+    case FN_ACKLEY: return go_xo<T, FN_ACKLEY>(L, xo, false);
+    case FN_GRIEWANK: return go_xo<T, FN_GRIEWANK>(L, xo, false);
     case FN_NONE: return go_xo<T, FN_NONE>(L, xo, false);
     default: return hipErrorInvalidValue;
   }

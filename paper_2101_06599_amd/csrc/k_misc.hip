@@ -83,10 +83,34 @@ __device__ T block_row_fitness(const T* x, const T* o, uint32_t D) {
   return canon(red[0] + red[1] + red[2] + red[3]);
 }
 
+// Ackley / Griewank: both row statistics, then their combination.
+template <typename T, int FN>
+__device__ T block_row_fitness2(const T* x, uint32_t D) {
+  __shared__ T red[8];
+  T s1 = T(0), s2 = stat2_init<T, FN>();
+  for (uint32_t j = threadIdx.x; j < D; j += blockDim.x) {
+    s1 += x[j] * x[j];
+    s2 = stat2_join<T, FN>(s2, stat2_term<T, FN>(x[j], j));
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_stat2<T, FN>(s2);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = s1;
+    red[4 + (threadIdx.x >> 6)] = s2;
+  }
+  __syncthreads();
+  T t2 = stat2_init<T, FN>();
+  for (int w = 0; w < 4; ++w) t2 = stat2_join<T, FN>(t2, red[4 + w]);
+  return canon(stat2_finish<T, FN>(red[0] + red[1] + red[2] + red[3], t2, D));
+}
+
 template <typename T>
 __device__ T block_row_fitness_rt(int fn, const T* x, const T* o, uint32_t D) {
   if (fn == FN_SPHERE) return block_row_fitness<T, FN_SPHERE>(x, o, D);
   if (fn == FN_RASTRIGIN) return block_row_fitness<T, FN_RASTRIGIN>(x, o, D);
+  if (fn == FN_ACKLEY) return block_row_fitness2<T, FN_ACKLEY>(x, D);
+  if (fn == FN_GRIEWANK) return block_row_fitness2<T, FN_GRIEWANK>(x, D);
   return block_row_fitness<T, FN_ROSENBROCK>(x, o, D);
 }
 
@@ -286,6 +310,32 @@ __global__ void __launch_bounds__(256) k_best_fp64(const RunDev* __restrict__ ru
   const T* x = static_cast<const T*>(P.X[cur[i]]) + i * P.ld;
   const T* o = static_cast<const T*>(P.o);
   __shared__ double red[4];
+  if (P.fn == FN_ACKLEY || P.fn == FN_GRIEWANK) {
+    // FP64 re-evaluation of the stored-precision row
+    double s1 = 0.0, s2 = P.fn == FN_GRIEWANK ? 1.0 : 0.0;
+    for (uint32_t j = threadIdx.x; j < D; j += blockDim.x) {
+      const double xj = static_cast<double>(x[j]);
+      s1 += xj * xj;
+      s2 = P.fn == FN_GRIEWANK ? s2 * stat2_term<double, FN_GRIEWANK>(xj, j)
+                               : s2 + stat2_term<double, FN_ACKLEY>(xj, j);
+    }
+    s1 = wave_sum(s1);
+    s2 = P.fn == FN_GRIEWANK ? wave_stat2<double, FN_GRIEWANK>(s2) : wave_sum(s2);
+    __shared__ double red2[4];
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6] = s1;
+      red2[threadIdx.x >> 6] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double t1 = red[0] + red[1] + red[2] + red[3];
+      const double f = P.fn == FN_GRIEWANK
+                           ? stat2_finish<double, FN_GRIEWANK>(t1, red2[0] * red2[1] * red2[2] * red2[3], D)
+                           : stat2_finish<double, FN_ACKLEY>(t1, red2[0] + red2[1] + red2[2] + red2[3], D);
+      *out = canon(f);
+    }
+    return;
+  }
   double acc = 0.0;
   if (P.fn == FN_ELLIPSOID) {
     // z_k = sum_j M_kj (x_j - o_j) with the caller's FP64 M
@@ -350,7 +400,8 @@ static inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n 
 hipError_t launch_init_impl(const RunDev* runs, const RunDev& h, int run, double lo, double hi,
                             double olo, double ohi, const void* shift, hipStream_t s) {
   const int64_t n = h.N * h.ld;
-  const int gen_shift = h.fn != FN_SPHERE && shift == nullptr;
+  const bool shifted = h.fn == FN_RASTRIGIN || h.fn == FN_ROSENBROCK || h.fn == FN_ELLIPSOID;
+  const int gen_shift = shifted && shift == nullptr;
   if (h.dtype == 0)
     hipLaunchKernelGGL(k_init<double>, dim3(nblk(n, 256)), dim3(256), 0, s, runs, run, lo, hi, olo,
                        ohi, static_cast<const double*>(shift), gen_shift);

@@ -46,3 +46,15 @@ ELLIPSOID_D2048 = dict(N=4096, D=2048, F=0.5, CR=0.9, fn="ellipsoid_rot", lo=-10
                        olo=-80.0, ohi=80.0, seed=0)
 ROSENBROCK_D10000 = dict(N=8192, D=10000, F=0.5, CR=0.9, fn="rosenbrock", dtype="fp32",
                          lo=-5.12, hi=5.12, olo=-4.0, ohi=4.0, seed=0)
+
+# The three runs of Table 2 (Sec. 4): function, D, N, F, Cr and generation
+# count as listed there, search box as given with each function.  The
+# Rosenbrock of Sec. 4 has its optimum at x = 1, which is the shifted form
+# z = x - o + 1 with o = 1 (olo = ohi = 1 makes every o_j exactly 1).
+ACKLEY_D1000 = dict(N=500, D=1000, F=0.5, CR=0.2, fn="ackley", dtype="fp64", lo=-30.0, hi=30.0,
+                    seed=0, gens=30000)
+GRIEWANK_D500 = dict(N=300, D=500, F=0.25, CR=0.45, fn="griewank", dtype="fp64", lo=-400.0,
+                     hi=400.0, seed=0, gens=20000)
+ROSENBROCK_D50 = dict(N=100, D=50, F=0.65, CR=0.95, fn="rosenbrock", dtype="fp64", lo=-5.12,
+                      hi=5.12, olo=1.0, ohi=1.0, seed=0, gens=10000)
+TABLE2 = {"ackley": ACKLEY_D1000, "griewank": GRIEWANK_D500, "rosenbrock": ROSENBROCK_D50}

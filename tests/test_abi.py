@@ -56,6 +56,16 @@ def test_workspace_size_and_validation(lib):
     with pytest.raises(de.DEError) as e:
         de.workspace_size([good(), good(dtype="fp32")])
     assert e.value.status == de.E_UNSUPPORTED
+    for fn in ("ackley", "griewank"):  # single runs only
+        assert de.workspace_size([good(fn=fn, olo=float("nan"))]) > 0  # no shift to draw
+        with pytest.raises(de.DEError) as e:
+            de.workspace_size([good(), good(fn=fn)])
+        assert e.value.status == de.E_UNSUPPORTED
+    keep: list = []
+    d = de._desc(good(), keep)
+    d.fn = 6
+    n = C.c_size_t(0)
+    assert lib.de_workspace_size((de.RunDesc * 1)(d), 1, C.byref(n)) == de.E_INVALID
 
 
 def test_init_rejects_bad_workspace_without_touching_gpu(lib):

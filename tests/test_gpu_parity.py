@@ -134,6 +134,86 @@ def test_row_width_invariance(cfg):
         assert np.all(np.abs(o[2] - outs[0][2]) <= tol * np.abs(outs[0][2]))
 
 
+# ---- Ackley and Griewank (Sec. 4), the Table 2 runs ----------------------
+
+def table2(name, **kw):
+    from paper_2101_06599_amd import synth
+    d = dict(synth.TABLE2[name], xo="nec")
+    d.pop("gens")
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("xo", ["nec", "bin", "exp"])
+@pytest.mark.parametrize("name", ["ackley", "griewank", "rosenbrock"])
+def test_table2_runs(name, xo, dtype):
+    gens = {"ackley": 3, "griewank": 5, "rosenbrock": 40}[name]
+    run_parity(table2(name, xo=xo, dtype=dtype, exp_impl="scan"), gens)
+
+
+@pytest.mark.parametrize("D", [1, 2, 7, 1037, 4500, 17001])
+@pytest.mark.parametrize("name", ["ackley", "griewank"])
+def test_two_statistic_row_shapes(name, D):
+    run_parity(table2(name, D=D, N=8 if D > 4000 else 12, xo="bin"), 2)
+
+
+@pytest.mark.parametrize("name", ["ackley", "griewank"])
+def test_two_statistic_row_width_invariance(name):
+    cfg = table2(name, D=1501, N=24, xo="nec")
+    outs = []
+    for tpr in (64, 256, 512, 1024):
+        gpu = DE([dict(cfg, tpr=tpr)])
+        tr = gpu.trace(0)
+        gpu.generation(1)
+        outs.append((tr["idx"].cpu().numpy().copy(), tr["trial"].cpu().numpy().copy(),
+                     tr["ftrial"].cpu().numpy().astype(np.float64)))
+        gpu.close()
+    ref = oracle_run(cfg)
+    rt = ref.generation(1, trace=True)
+    phi = oracle.fitness_phi(name, rt["trial"])
+    for o in outs:
+        assert np.array_equal(o[0][:, :5], rt["idx"][:, :5])
+        assert np.array_equal(o[1], rt["trial"])
+        assert np.all(np.abs(o[2] - rt["ftrial"]) <= tol_of(cfg) * phi)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["ackley", "griewank"])
+def test_two_statistic_evaluate_special_points(name, dtype):
+    """de_evaluate at the optimum, integer / cosine points and random rows."""
+    import torch
+    D = 777
+    cfg = table2(name, D=D, N=8, dtype=dtype)
+    gpu = DE([cfg])
+    j = np.arange(1, D + 1, dtype=np.float64)
+    rows = [np.zeros(D), np.full(D, 3.0), np.full(D, -0.5), 2 * np.pi * np.sqrt(j),
+            np.pi * np.sqrt(j)]
+    rows += list(np.random.default_rng(4).uniform(cfg["lo"], cfg["hi"], (40, D)))
+    dt = torch.float64 if dtype == "fp64" else torch.float32
+    Xd = torch.as_tensor(np.array(rows), dtype=dt, device="cuda:0")
+    Xr = Xd.cpu().numpy().astype(np.float64)
+    f = gpu.evaluate(0, Xd).cpu().numpy().astype(np.float64)
+    fr = oracle.fitness(name, Xr)
+    phi = oracle.fitness_phi(name, Xr)
+    assert np.all(np.abs(f - fr) <= tol_of(cfg) * phi)
+    assert f[0] == 0.0 or abs(f[0]) <= 1e-15
+
+
+@pytest.mark.parametrize("name", ["ackley", "griewank"])
+def test_two_statistic_best_and_many_generations(name):
+    """200 generations at Table 2's F and Cr (smaller N, D): selection and the
+    best-so-far stay with the oracle; best f is the FP64 value of the row."""
+    cfg = table2(name, D=64, N=40, xo="nec", dtype="fp32")
+    gpu, ref, flips = run_parity(cfg, 200)
+    f, idx, g, x = gpu.best(0)
+    rf, ridx, rg, rx = ref.best()
+    fr = oracle.fitness(name, x.astype(np.float64))
+    assert abs(f - fr) <= 1e-12 * oracle.fitness_phi(name, x.astype(np.float64))
+    if flips == 0:
+        assert (idx, g) == (ridx, rg)
+
+
 # ---- rotated ellipsoid on the matrix cores ---------------------------------
 
 def ell(mm, dtype, **kw):
