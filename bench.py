@@ -15,7 +15,10 @@ The same JSON line carries:
   variants      bin / classic exp (three GPU mappings) / NEC x FP64 / FP32;
   rosenbrock    shifted Rosenbrock D = 10000, N = 8192, FP32 (HBM-sized);
   rotated       rotated ellipsoid D = 2048, N = 4096: product TFLOP/s per mode;
-  batched       512 independent NEC runs of uneven shape in one launch.
+  batched       512 independent NEC runs of uneven shape in one launch;
+  table1_masks  the crossover-only grid of Table 1 (masks written to HBM);
+  paper_runs    the three runs of Table 2 (Ackley, Griewank, Rosenbrock) end
+                to end, with best value and generation reached.
 """
 from __future__ import annotations
 
@@ -191,6 +194,46 @@ def table1(torch, de, reps=100):
     return res
 
 
+# Tables 3-5 of the paper (Sec. 4, GTX 760, CuPy): the CUDA-DE rows,
+# variant -> (best value, generation of the best, seconds for the whole run).
+# "L" is the new exponential crossover (our "nec").
+PAPER_TABLE345 = {
+    "ackley": {"nec": (2.62e-05, 29991, 323.97), "bin": (2.28e-04, 29983, 321.45)},
+    "griewank": {"nec": (1.73e-16, 19936, 149.03), "bin": (2.22e-16, 6041, 143.95)},
+    "rosenbrock": {"nec": (1.16e-07, 9996, 58.92), "bin": (9.93e-10, 10000, 56.72)},
+}
+
+
+def paper_runs(torch, de, synth):
+    """The three runs of Table 2 end to end (every generation, FP64), with
+    the best value and generation each reaches; the paper's CUDA-DE figures
+    sit beside them as context (other hardware, other random streams)."""
+    res = {}
+    for name, base in synth.TABLE2.items():
+        for xo in ("nec", "bin"):
+            cfg = dict(base, xo=xo)
+            gens = cfg.pop("gens")
+            h = de.DE([cfg])
+            s = torch.cuda.current_stream()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(s)
+            h.generation(gens)
+            e1.record(s)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3
+            f, idx, g, _ = h.best(0)
+            pv, pg, pt = PAPER_TABLE345[name][xo]
+            res[f"{name}_D{cfg['D']}_N{cfg['N']}_{xo}"] = {
+                "generations": gens, "time_s": t, "us_per_gen": t / gens * 1e6,
+                "best_value": f, "best_gen": g,
+                "paper_cuda": {"best_value": pv, "best_gen": pg, "time_s": pt},
+                "speedup_vs_paper": pt / t}
+            h.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,7 +241,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections", default="all",
                     help="comma list of: head (headline only), variants, rosenbrock, rotated, "
-                         "batched, table1, tuning, cpu, copy (default: all but copy)")
+                         "batched, table1, paper_runs, tuning, cpu, copy (default: all but copy)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -212,7 +255,7 @@ def main():
     torch.cuda.set_device(0)
     de.lib()
     secs = set(args.sections.split(",")) if args.sections != "all" else {
-        "variants", "rosenbrock", "rotated", "batched", "table1", "tuning", "cpu"}
+        "variants", "rosenbrock", "rotated", "batched", "table1", "paper_runs", "tuning", "cpu"}
     K, W = args.steps, args.warmup
 
     head = dict(synth.RASTRIGIN_D1000, xo="nec", dtype="fp64")
@@ -310,6 +353,9 @@ def main():
 
     if "table1" in secs:
         out["table1_masks"] = table1(torch, de)
+
+    if "paper_runs" in secs:
+        out["paper_runs"] = paper_runs(torch, de, synth)
 
     if "tuning" in secs:
         from paper_2101_06599_amd.tune import tune_tpr

@@ -209,12 +209,14 @@ Layout layout(const de_run_desc* runs, int32_t n_runs) {
 int pick_tpr(const de_run_desc& d, bool batched) {
   if (batched) return 64;
   if (d.tpr != 0) return d.tpr;
-  // measured defaults: a row held in registers by as few lanes as fit
+  // measured defaults: a row held in registers by as few lanes as fit ...
   const int64_t nchunk = (d.D + 3) / 4;
-  if (nchunk <= 64 * 4) return 64;
-  if (nchunk <= 256 * 4) return 256;
-  if (nchunk <= 512 * 5) return 512;
-  return 1024;
+  int t = nchunk <= 64 * 4 ? 64 : nchunk <= 256 * 4 ? 256 : nchunk <= 512 * 5 ? 512 : 1024;
+  // ... widened while the run has fewer wavefronts than the chip has SIMDs
+  // (256 CUs x 4) and every lane still has more than one chunk: small
+  // populations then finish each row in fewer dependent steps.
+  while (t < 1024 && nchunk > t && d.N * (t / 64) < 1024) t = t == 64 ? 256 : 2 * t;
+  return t;
 }
 
 hipError_t upload_run(de_handle* h, int r, hipStream_t s) {

@@ -2,7 +2,7 @@
 
 The lanes given to one individual (`tpr`: 64, 256, 512 or 1024) trade the
 number of rows in flight against per-row work; the library's default follows
-D only.  tune_tpr() times every candidate on a scratch handle of the same
+D and N.  tune_tpr() times every candidate on a scratch handle of the same
 shape (results never depend on tpr) and keeps the fastest per device and run
 shape in a small JSON cache next to this file."""
 from __future__ import annotations
