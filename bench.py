@@ -17,6 +17,7 @@ The same JSON line carries:
   rotated       rotated ellipsoid D = 2048, N = 4096: product TFLOP/s per mode;
   batched       512 independent NEC runs of uneven shape in one launch;
   table1_masks  the crossover-only grid of Table 1 (masks written to HBM);
+  fig456_nec_vs_pexp  the NEC / p-exp mask sweep of Figs 4-6;
   paper_runs    the three runs of Table 2 (Ackley, Griewank, Rosenbrock) end
                 to end, with best value and generation reached.
 """
@@ -194,6 +195,43 @@ def table1(torch, de, reps=100):
     return res
 
 
+def fig456(torch, de, reps=100):
+    """Figs 4-6 of the paper: crossover-mask time of NEC against the classic
+    exponential crossover with one work-item per individual (p-exp), for
+    N in {100, 1000, 5000} and D from 2 to 5000, 100 generations per point.
+    The figures do not name Cr: each point sums Cr in {0.2, ..., 1.0} as
+    Table 1 does.  The wavefront-scan mapping of the classic crossover is
+    timed beside them."""
+    res = {}
+    for N in (100, 1000, 5000):
+        for D in (2, 10, 50, 100, 500, 1000, 2000, 5000):
+            row = {}
+            for name, xo, impl in (("nec", "nec", "lane"), ("p_exp", "exp", "job"),
+                                   ("exp_scan", "exp", "scan")):
+                total = 0.0
+                out = torch.empty((N, D), dtype=torch.uint8, device="cuda:0")
+                for CR in (0.2, 0.4, 0.6, 0.8, 1.0):
+                    h = de.DE([dict(N=N, D=D, CR=CR, xo=xo, exp_impl=impl, fn="sphere",
+                                    dtype="fp32", seed=0)])
+                    h.masks(0, 1, out)
+                    s = torch.cuda.current_stream()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    torch.cuda.synchronize()
+                    e0.record(s)
+                    for g in range(1, reps + 1):
+                        h.masks(0, g, out)
+                    e1.record(s)
+                    torch.cuda.synchronize()
+                    total += e0.elapsed_time(e1) / 1e3
+                    h.close()
+                row[name + "_s"] = total
+                del out
+            row["p_exp_over_nec"] = row["p_exp_s"] / row["nec_s"]
+            res[f"N{N}_D{D}"] = row
+    return res
+
+
 # Tables 3-5 of the paper (Sec. 4, GTX 760, CuPy): the CUDA-DE rows,
 # variant -> (best value, generation of the best, seconds for the whole run).
 # "L" is the new exponential crossover (our "nec").
@@ -204,33 +242,40 @@ PAPER_TABLE345 = {
 }
 
 
-def paper_runs(torch, de, synth):
-    """The three runs of Table 2 end to end (every generation, FP64), with
-    the best value and generation each reaches; the paper's CUDA-DE figures
-    sit beside them as context (other hardware, other random streams)."""
+def paper_runs(torch, de, synth, seeds=(0, 1, 2, 3, 4)):
+    """The three runs of Table 2 end to end (every generation, FP64) over
+    several seeds: time per run and the best value and generation each seed
+    reaches.  The paper's CUDA-DE figures sit beside them as context (other
+    hardware, other random streams, one run each)."""
     res = {}
     for name, base in synth.TABLE2.items():
         for xo in ("nec", "bin"):
-            cfg = dict(base, xo=xo)
-            gens = cfg.pop("gens")
-            h = de.DE([cfg])
-            s = torch.cuda.current_stream()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record(s)
-            h.generation(gens)
-            e1.record(s)
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) / 1e3
-            f, idx, g, _ = h.best(0)
+            times, vals, gens_best = [], [], []
+            for seed in seeds:
+                cfg = dict(base, xo=xo, seed=seed)
+                gens = cfg.pop("gens")
+                h = de.DE([cfg])
+                s = torch.cuda.current_stream()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record(s)
+                h.generation(gens)
+                e1.record(s)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1) / 1e3)
+                f, _, g, _ = h.best(0)
+                vals.append(f)
+                gens_best.append(g)
+                h.close()
             pv, pg, pt = PAPER_TABLE345[name][xo]
-            res[f"{name}_D{cfg['D']}_N{cfg['N']}_{xo}"] = {
-                "generations": gens, "time_s": t, "us_per_gen": t / gens * 1e6,
-                "best_value": f, "best_gen": g,
+            t = sum(times) / len(times)
+            res[f"{name}_D{base['D']}_N{base['N']}_{xo}"] = {
+                "generations": base["gens"], "seeds": list(seeds), "time_s_mean": t,
+                "us_per_gen": t / base["gens"] * 1e6, "best_values": vals,
+                "best_value_median": sorted(vals)[len(vals) // 2], "best_gens": gens_best,
                 "paper_cuda": {"best_value": pv, "best_gen": pg, "time_s": pt},
                 "speedup_vs_paper": pt / t}
-            h.close()
     return res
 
 
@@ -241,7 +286,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections", default="all",
                     help="comma list of: head (headline only), variants, rosenbrock, rotated, "
-                         "batched, table1, paper_runs, tuning, cpu, copy (default: all but copy)")
+                         "batched, table1, fig456, paper_runs, tuning, cpu, copy (default: all "
+                         "but copy)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -255,7 +301,8 @@ def main():
     torch.cuda.set_device(0)
     de.lib()
     secs = set(args.sections.split(",")) if args.sections != "all" else {
-        "variants", "rosenbrock", "rotated", "batched", "table1", "paper_runs", "tuning", "cpu"}
+        "variants", "rosenbrock", "rotated", "batched", "table1", "fig456", "paper_runs", "tuning",
+        "cpu"}
     K, W = args.steps, args.warmup
 
     head = dict(synth.RASTRIGIN_D1000, xo="nec", dtype="fp64")
@@ -353,6 +400,9 @@ def main():
 
     if "table1" in secs:
         out["table1_masks"] = table1(torch, de)
+
+    if "fig456" in secs:
+        out["fig456_nec_vs_pexp"] = fig456(torch, de)
 
     if "paper_runs" in secs:
         out["paper_runs"] = paper_runs(torch, de, synth)

@@ -163,7 +163,10 @@ de_status de_set_state(de_handle* h, int32_t run, const void* pop_host, const vo
  * number) of one run, exactly as that generation applies them: the N x D
  * 0/1 matrix that Alg 7 (binomial) and Alg 10 (NEC) return, or the run of
  * Alg 8 (classic exponential), one byte per element, row-major, written to
- * the device buffer `mask` (N * D bytes, caller-owned).  Does not change the
+ * the device buffer `mask` (N * D bytes, caller-owned).  The run's exp_impl
+ * picks the classic exponential mapping: DE_EXP_JOB has one work-item per
+ * individual walk Alg 8 and write its row (Sec. 3.1's p-exp); LANE and SCAN
+ * use a wavefront per row.  All give the same bytes.  Does not change the
  * run's state.  Asynchronous. */
 de_status de_masks(de_handle* h, int32_t run, int64_t gen, uint8_t* mask, void* stream);
 

@@ -53,9 +53,43 @@ __global__ void __launch_bounds__(256) k_masks(const RunDev* __restrict__ runs, 
   }
 }
 
+// Classic exponential masks with one work-item per individual (the p-exp
+// mapping of Sec. 3.1): the work-item walks Alg 8 from j_rand, marking one
+// element per passed draw, then writes the zeros of the rest of its row in
+// the same walking order.
+__global__ void __launch_bounds__(64) k_masks_job(const RunDev* __restrict__ runs, int32_t run,
+                                                  uint32_t g, uint8_t* __restrict__ out) {
+  const RunDev& P = runs[run];
+  const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const uint32_t jr = scale_index(draw(P, TAG_XO, g, i, 0).x, D);
+  DE_GLOBAL uint8_t* o = gmut<uint8_t>(out) + static_cast<int64_t>(i) * D;
+  uint32_t j = jr, L = 0, e = 0;
+  uint4 b = make_uint4(0, 0, 0, 0);
+  bool more;
+  do {
+    o[j] = 1;
+    j = (j + 1 == D) ? 0 : j + 1;
+    ++L;
+    if ((e & 3u) == 0) b = draw(P, TAG_EXP, g, i, e >> 2);
+    more = static_cast<uint64_t>(word_of(b, e & 3u)) < P.thr && L < D;
+    ++e;
+  } while (more);
+  for (; L < D; ++L) {
+    o[j] = 0;
+    j = (j + 1 == D) ? 0 : j + 1;
+  }
+}
+
 hipError_t launch_masks(const RunDev* runs, const RunDev& h, int run, uint32_t g, uint8_t* out,
                         hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>((h.N + 3) / 4);
+  if (h.xo == XO_EXP && h.exp_impl == EXPI_JOB) {
+    hipLaunchKernelGGL(k_masks_job, dim3(static_cast<unsigned>((h.N + 63) / 64)), dim3(64), 0, s,
+                       runs, run, g, out);
+    return hipGetLastError();
+  }
   switch (h.xo) {
     case XO_BIN: hipLaunchKernelGGL(k_masks<XO_BIN>, dim3(blocks), dim3(256), 0, s, runs, run, g, out); break;
     case XO_EXP: hipLaunchKernelGGL(k_masks<XO_EXP>, dim3(blocks), dim3(256), 0, s, runs, run, g, out); break;

@@ -504,7 +504,7 @@ def oracle_mask(seed, D, CR, xo, g, i):
 
 
 @pytest.mark.parametrize("xo,impl", [("bin", "lane"), ("exp", "scan"), ("exp", "lane"),
-                                     ("nec", "lane")])
+                                     ("exp", "job"), ("nec", "lane")])
 @pytest.mark.parametrize("D,N,CR", [(10, 100, 0.2), (13, 37, 0.6), (1000, 64, 0.8),
                                     (100, 30, 1.0), (257, 20, 0.0), (1, 5, 0.5)])
 def test_masks_match_oracle(xo, impl, D, N, CR):
