@@ -22,7 +22,9 @@ XO = {"bin": 0, "exp": 1, "nec": 2}
 FN = {"sphere": 0, "rastrigin": 1, "rosenbrock": 2, "ellipsoid_rot": 3, "ackley": 4,
       "griewank": 5}
 DTYPE = {"fp64": 0, "fp32": 1}
-TAG = {"init": 1, "shift": 2, "idx": 3, "xo": 4, "bin": 5, "exp": 6}
+TAG = {"init": 1, "shift": 2, "idx": 3, "xo": 4, "bin": 5, "exp": 6, "offset": 7, "perm": 8,
+       "shuffle": 9}
+BASE = {"classic": 0, "random": 1, "offset": 2, "perm": 3}
 
 
 def build(force: bool = True) -> str:
@@ -41,7 +43,8 @@ class _Desc(C.Structure):
                 ("xo", C.c_int32), ("fn", C.c_int32), ("dtype", C.c_int32), ("run", C.c_int32),
                 ("lo", C.c_double), ("hi", C.c_double), ("olo", C.c_double), ("ohi", C.c_double),
                 ("seed", C.c_uint64), ("shift", C.c_void_p), ("rot", C.c_void_p),
-                ("lazy", C.c_int32), ("pad", C.c_int32)]
+                ("lazy", C.c_int32), ("base", C.c_int32), ("shuffle", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 def lib():
@@ -65,6 +68,11 @@ def lib():
         L.oracle_skip.argtypes = [C.c_int64, i64p, C.c_int]
         L.oracle_skip.restype = C.c_int64
         L.oracle_indices.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_uint32, C.c_int64, i64p]
+        L.oracle_indices_scheme.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_int64, C.c_uint32,
+                                            C.c_int64, i64p]
+        L.oracle_permute.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64,
+                                     C.c_int64]
+        L.oracle_permute.restype = C.c_int64
         L.oracle_mask_bin.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_double, C.c_uint32,
                                       C.c_int64, C.c_int64, u8p]
         L.oracle_exp_length.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_double, C.c_uint32,
@@ -133,6 +141,19 @@ def indices(seed, run, N, g, i):
     r = np.zeros(3, np.int64)
     lib().oracle_indices(seed, run, N, g, i, r)
     return r
+
+
+def indices_scheme(seed, run, base, N, g, i):
+    """r0, r1, r2 of position i under base scheme `base` (BASE name)."""
+    r = np.zeros(3, np.int64)
+    lib().oracle_indices_scheme(seed, run, BASE[base], N, g, i, r)
+    return r
+
+
+def permute(seed, run, tag, g, N, k) -> int:
+    """Image of k under the keyed permutation of [0, N) (tag name or number)."""
+    t = TAG[tag] if isinstance(tag, str) else int(tag)
+    return int(lib().oracle_permute(seed, run, t, g, N, k))
 
 
 def mask_bin(seed, run, D, CR, g, i, jrand):
@@ -209,7 +230,8 @@ class Run:
     hold float32 values exactly)."""
 
     def __init__(self, N, D, F=0.5, CR=0.9, xo="bin", fn="sphere", dtype="fp64", lo=-100.0,
-                 hi=100.0, olo=0.0, ohi=0.0, seed=0, run=0, shift=None, rot=None, lazy=False):
+                 hi=100.0, olo=0.0, ohi=0.0, seed=0, run=0, shift=None, rot=None, lazy=False,
+                 base="classic", shuffle=False):
         self.N, self.D = int(N), int(D)
         self.dtype = dtype
         self.fn = fn
@@ -220,7 +242,8 @@ class Run:
         d = _Desc(N=self.N, D=self.D, F=F, CR=CR, xo=XO[xo], fn=FN[fn], dtype=DTYPE[dtype], run=run,
                   lo=lo, hi=hi, olo=olo, ohi=ohi, seed=seed,
                   shift=None if sh is None else sh.ctypes.data,
-                  rot=None if rt is None else rt.ctypes.data, lazy=1 if lazy else 0)
+                  rot=None if rt is None else rt.ctypes.data, lazy=1 if lazy else 0,
+                  base=BASE[base], shuffle=1 if shuffle else 0)
         self._h = lib().oracle_create(C.byref(d))
         if not self._h:
             raise ValueError("oracle_create rejected the run description")

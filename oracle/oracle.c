@@ -89,6 +89,75 @@ void oracle_indices(uint64_t seed, uint32_t run, int64_t N, uint32_t g, int64_t 
   r[2] = oracle_skip(oracle_randint(w2, N - 3), e3, 3);
 }
 
+/* A keyed pseudo-random permutation of [0, N) for generation g, used where
+ * the paper shuffles (Alg 2 line 5, Alg 5).  The paper names no shuffling
+ * method; this reading takes a balanced eight-round Feistel network (Luby and
+ * Rackoff) on m-bit integers, m even with 2^m >= N (m >= 2), and walks the
+ * cycle (Black and Rogaway) until the image falls inside [0, N).  Round r
+ * swaps the halves and XORs mix(R ^ K_r) into the new right half; K_r is word
+ * r%4 of Philox block r/4 (individual 0, generation g, tag).  mix is the
+ * 32-bit integer hash x ^= x>>16; x *= 0x7feb352d; x ^= x>>15;
+ * x *= 0x846ca68b; x ^= x>>16.  Eight rounds keep even 4-bit domains close
+ * to uniform. */
+static uint32_t perm_mix(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+int64_t oracle_permute(uint64_t seed, uint32_t run, uint32_t tag, uint32_t g, int64_t N, int64_t k) {
+  int m = 2;
+  while (((int64_t)1 << m) < N) m += 2;
+  const int h = m / 2;
+  const uint32_t hmask = (1u << h) - 1u;
+  uint32_t K[8];
+  for (int r = 0; r < 8; ++r) K[r] = oracle_word(seed, run, tag, g, 0, (uint32_t)(r / 4), r % 4);
+  uint32_t x = (uint32_t)k;
+  do {
+    uint32_t L = x >> h, R = x & hmask;
+    for (int r = 0; r < 8; ++r) {
+      uint32_t t = L ^ (perm_mix(R ^ K[r]) & hmask);
+      L = R;
+      R = t;
+    }
+    x = (L << h) | R;
+  } while ((int64_t)x >= N);
+  return (int64_t)x;
+}
+
+/* Base index selection for row (position) i of generation g.
+ *   OR_BASE_CLASSIC: r0, r1, r2 as in oracle_indices (Alg 1, distinct, != i).
+ *   OR_BASE_RANDOM:  Alg 3, r0 = floor(N U) (IDX word 0).
+ *   OR_BASE_OFFSET:  Alg 4, r0 = (i + r_g) mod N with one r_g = ceil((N-1) U)
+ *                    per generation, drawn as 1 + randint(N-1) from word 0 of
+ *                    the OFFSET block (block 0, individual 0, generation g).
+ *   OR_BASE_PERM:    Alg 5, r0 = sigma_g(i), sigma_g = oracle_permute(PERM tag).
+ * The three paper schemes take r1, r2 from Alg 6: r1 = (r0 + o1) mod N and
+ * r2 = (r1 + o2) mod N with o = ceil((N-1) U), drawn as 1 + randint(N-1) from
+ * IDX words 1 and 2 (so r1 != r0 and r2 != r1; nothing else is excluded). */
+void oracle_indices_scheme(uint64_t seed, uint32_t run, int base, int64_t N, uint32_t g, int64_t i,
+                           int64_t r[3]) {
+  if (base == OR_BASE_CLASSIC) {
+    oracle_indices(seed, run, N, g, i, r);
+    return;
+  }
+  if (base == OR_BASE_RANDOM) {
+    r[0] = oracle_randint(oracle_word(seed, run, OR_TAG_IDX, g, (uint32_t)i, 0, 0), N);
+  } else if (base == OR_BASE_OFFSET) {
+    int64_t rg = 1 + oracle_randint(oracle_word(seed, run, OR_TAG_OFFSET, g, 0, 0, 0), N - 1);
+    r[0] = (i + rg) % N;
+  } else {
+    r[0] = oracle_permute(seed, run, OR_TAG_PERM, g, N, i);
+  }
+  int64_t o1 = 1 + oracle_randint(oracle_word(seed, run, OR_TAG_IDX, g, (uint32_t)i, 0, 1), N - 1);
+  int64_t o2 = 1 + oracle_randint(oracle_word(seed, run, OR_TAG_IDX, g, (uint32_t)i, 0, 2), N - 1);
+  r[1] = (r[0] + o1) % N;
+  r[2] = (r[1] + o2) % N;
+}
+
 /* Alg 7 / Eq 2: element j crosses if rand < Cr or j = j_rand.  The rand of
  * element j is word j%4 of BIN block j/4. */
 void oracle_mask_bin(uint64_t seed, uint32_t run, int64_t D, double CR, uint32_t g, int64_t i,
@@ -326,6 +395,7 @@ static void update_best(oracle_state* s) {
 
 oracle_state* oracle_create(const oracle_desc* d) {
   if (d->N < 4 || d->D < 1 || d->N >= (1 << 21) || d->D >= (1 << 21)) return NULL;
+  if (d->base < OR_BASE_CLASSIC || d->base > OR_BASE_PERM) return NULL;
   if (d->fn == OR_FN_ELLIPSOID_ROT && (d->rot == NULL || d->D < 2)) return NULL;
   oracle_state* s = (oracle_state*)calloc(1, sizeof(oracle_state));
   s->d = *d;
@@ -372,21 +442,26 @@ void oracle_destroy(oracle_state* s) {
   free(s->tr); free(s->mask); free(s->rot); free(s);
 }
 
-/* One generation, Alg 2 lines 5-14 (without the shuffle of line 5): for every
- * individual choose r0, r1, r2, build the crossover mask first (line 7), copy
- * x into u and overwrite the masked elements with the DE/rand/1 mutant
- * x_r0 + F (x_r1 - x_r2) (lines 8-9, Eq 1), evaluate u (line 10), then keep
- * u_i wherever f(u_i) < f_i strictly (lines 11-14, Alg 1 line 10). */
-/* Generation g's trial for individual i from population x (Alg 2 lines 6-10
+/* Storage row of position k in generation g: with the shuffle of Alg 2
+ * line 5 the individuals are reordered by pi_g before anything else, so
+ * position k holds the individual stored in row pi_g(k); without it, k. */
+static int64_t row_of(const oracle_desc* d, uint32_t g, int64_t k) {
+  return d->shuffle ? oracle_permute(d->seed, (uint32_t)d->run, OR_TAG_SHUFFLE, g, d->N, k) : k;
+}
+
+/* Generation g's trial for position i from population x (Alg 2 lines 6-10
  * for one row): choose r0, r1, r2, build the crossover mask first (line 7),
- * copy x_i and overwrite the masked elements with the DE/rand/1 mutant
- * x_r0 + F (x_r1 - x_r2) (lines 8-9, Eq 1), then evaluate (line 10). */
+ * copy the individual at position i and overwrite the masked elements with
+ * the DE/rand/1 mutant x_r0 + F (x_r1 - x_r2) (lines 8-9, Eq 1), then
+ * evaluate (line 10).  Draws are addressed by position; t[0..2] are the
+ * storage rows of r0, r1, r2. */
 static void build_trial(const oracle_state* s, const double* x, uint32_t g, int64_t i,
                         int64_t* t, uint8_t* m, double* ui, double* fu) {
   const oracle_desc* d = &s->d;
   int64_t N = d->N, D = d->D;
   int64_t r[3];
-  oracle_indices(d->seed, (uint32_t)d->run, N, g, i, r);
+  oracle_indices_scheme(d->seed, (uint32_t)d->run, d->base, N, g, i, r);
+  for (int a = 0; a < 3; ++a) r[a] = row_of(d, g, r[a]);
   uint32_t xw0 = oracle_word(d->seed, (uint32_t)d->run, OR_TAG_XO, g, (uint32_t)i, 0, 0);
   uint32_t xw1 = oracle_word(d->seed, (uint32_t)d->run, OR_TAG_XO, g, (uint32_t)i, 0, 1);
   int64_t jrand = oracle_randint(xw0, D);
@@ -403,7 +478,7 @@ static void build_trial(const oracle_state* s, const double* x, uint32_t g, int6
   const double* x0 = x + r[0] * D;
   const double* x1 = x + r[1] * D;
   const double* x2 = x + r[2] * D;
-  const double* xi = x + i * D;
+  const double* xi = x + row_of(d, g, i) * D;
   for (int64_t j = 0; j < D; ++j) {
     if (!m[j]) {
       ui[j] = xi[j];
@@ -418,15 +493,19 @@ static void build_trial(const oracle_state* s, const double* x, uint32_t g, int6
   t[0] = r[0]; t[1] = r[1]; t[2] = r[2]; t[3] = jrand; t[4] = L; t[5] = 0;
 }
 
-/* One generation, Alg 2 lines 5-14 (without the shuffle of line 5): every
- * trial is built from generation g-1, then u_i replaces x_i wherever
- * f(u_i) < f_i strictly (lines 11-14, Alg 1 line 10). */
+/* One generation, Alg 2 lines 5-14: every trial is built from generation
+ * g-1, then u_i replaces x_i wherever f(u_i) < f_i strictly (lines 11-14,
+ * Alg 1 line 10).  The shuffle of line 5 is a relabelling: position k works
+ * on storage row pi_g(k) and its result goes back to that row, so the
+ * population is never moved (see row_of).  Trace arrays are kept by row. */
 static void one_generation(oracle_state* s) {
   const oracle_desc* d = &s->d;
   int64_t N = d->N, D = d->D;
   uint32_t g = (uint32_t)(s->gen + 1);
-  for (int64_t i = 0; i < N; ++i)
-    build_trial(s, s->x, g, i, s->tr + 6 * i, s->mask + i * D, s->u + i * D, s->fu + i);
+  for (int64_t k = 0; k < N; ++k) {
+    int64_t i = row_of(d, g, k);
+    build_trial(s, s->x, g, k, s->tr + 6 * i, s->mask + i * D, s->u + i * D, s->fu + i);
+  }
   s->gen += 1;
   for (int64_t i = 0; i < N; ++i) {
     if (s->fu[i] < s->fit[i]) {
@@ -440,7 +519,11 @@ static void one_generation(oracle_state* s) {
 
 void oracle_individual(const oracle_state* s, const double* pop, int64_t g, int64_t i,
                        int64_t* idx6, uint8_t* mask, double* trial, double* ftrial) {
-  build_trial(s, pop, (uint32_t)g, i, idx6, mask, trial, ftrial);
+  int64_t k = i;
+  if (s->d.shuffle)  /* the position whose storage row is i */
+    for (k = 0; k < s->d.N && row_of(&s->d, (uint32_t)g, k) != i; ++k) {
+    }
+  build_trial(s, pop, (uint32_t)g, k, idx6, mask, trial, ftrial);
 }
 
 int oracle_generation(oracle_state* s, int64_t n, int64_t* trace_idx, uint8_t* trace_mask,

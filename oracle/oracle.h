@@ -34,7 +34,11 @@ enum { OR_XO_BIN = 0, OR_XO_EXP = 1, OR_XO_NEC = 2 };
 enum { OR_FN_SPHERE = 0, OR_FN_RASTRIGIN = 1, OR_FN_ROSENBROCK = 2, OR_FN_ELLIPSOID_ROT = 3,
        OR_FN_ACKLEY = 4, OR_FN_GRIEWANK = 5 };
 enum { OR_FP64 = 0, OR_FP32 = 1 };
-enum { OR_TAG_INIT = 1, OR_TAG_SHIFT = 2, OR_TAG_IDX = 3, OR_TAG_XO = 4, OR_TAG_BIN = 5, OR_TAG_EXP = 6 };
+enum { OR_TAG_INIT = 1, OR_TAG_SHIFT = 2, OR_TAG_IDX = 3, OR_TAG_XO = 4, OR_TAG_BIN = 5, OR_TAG_EXP = 6,
+       OR_TAG_OFFSET = 7, OR_TAG_PERM = 8, OR_TAG_SHUFFLE = 9 };
+/* base index selection: classic DE/rand/1 (r0, r1, r2 distinct and != i),
+ * or Alg 3 / Alg 4 / Alg 5 for r0 with Alg 6's offsets for r1, r2 */
+enum { OR_BASE_CLASSIC = 0, OR_BASE_RANDOM = 1, OR_BASE_OFFSET = 2, OR_BASE_PERM = 3 };
 
 /* ---- random numbers ---------------------------------------------------- */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -48,6 +52,11 @@ int64_t oracle_skip(int64_t r, const int64_t* excl, int n_excl);
 /* ---- operators (one individual) ---------------------------------------- */
 /* r0 (base), r1, r2 (difference pair) for individual i, generation g */
 void oracle_indices(uint64_t seed, uint32_t run, int64_t N, uint32_t g, int64_t i, int64_t r[3]);
+/* r0, r1, r2 for row (position) i under a base scheme (OR_BASE_*) */
+void oracle_indices_scheme(uint64_t seed, uint32_t run, int base, int64_t N, uint32_t g, int64_t i,
+                           int64_t r[3]);
+/* keyed pseudo-random permutation of [0, N) for generation g: image of k */
+int64_t oracle_permute(uint64_t seed, uint32_t run, uint32_t tag, uint32_t g, int64_t N, int64_t k);
 /* binomial mask (Alg 7, Eq 2) */
 void oracle_mask_bin(uint64_t seed, uint32_t run, int64_t D, double CR, uint32_t g, int64_t i,
                      int64_t jrand, uint8_t* mask);
@@ -83,6 +92,8 @@ typedef struct {
   const double* shift;  /* D values or NULL */
   const double* rot;    /* D x D row-major, rotated ellipsoid only */
   int32_t lazy;         /* 1: skip the initial evaluation (per-individual use only) */
+  int32_t base;         /* OR_BASE_* */
+  int32_t shuffle;      /* 1: shuffle the individuals every generation (Alg 2 line 5) */
   int32_t pad;
 } oracle_desc;
 
@@ -100,9 +111,10 @@ void oracle_set_state(oracle_state* s, const double* pop, const double* fit, int
                       double best_f, int64_t best_idx, int64_t best_gen);
 void oracle_get_best(const oracle_state* s, double* f, int64_t* idx, int64_t* gen, double* xbest);
 void oracle_get_shift(const oracle_state* s, double* o);
-/* Generation g's trial of individual i built from the population `pop`
- * (N x D, the population after generation g-1): idx6 = r0, r1, r2, jrand, L,
- * 0; mask and trial D values; *ftrial = f(trial). */
+/* Generation g's trial for the individual stored in row i, built from the
+ * population `pop` (N x D, the population after generation g-1): idx6 = r0,
+ * r1, r2 (rows read), jrand, L, 0; mask and trial D values; *ftrial =
+ * f(trial).  With the shuffle, row i is the one at position k = pi_g^-1(i). */
 void oracle_individual(const oracle_state* s, const double* pop, int64_t g, int64_t i,
                        int64_t* idx6, uint8_t* mask, double* trial, double* ftrial);
 
