@@ -87,6 +87,25 @@ typedef enum {
 
 typedef enum { DE_FP64 = 0, DE_FP32 = 1 } de_dtype;
 
+/* Base index selection (Sec. 2).
+ *   DE_BASE_CLASSIC: r0, r1, r2 uniform, mutually distinct and != i (Alg 1).
+ *   DE_BASE_RANDOM:  Alg 3, r0 uniform on [0, N) (may equal i).
+ *   DE_BASE_OFFSET:  Alg 4, r0 = (i + r_g) mod N, one r_g in [1, N-1] per
+ *                    generation.
+ *   DE_BASE_PERM:    Alg 5, r0 = sigma_g(i), a fresh pseudo-random
+ *                    permutation of [0, N) every generation.
+ * RANDOM, OFFSET and PERM take the difference pair from Alg 6:
+ * r1 = (r0 + o1) mod N, r2 = (r1 + o2) mod N with o1, o2 uniform on [1, N-1].
+ * The permutation is an eight-round keyed Feistel network on the smallest
+ * even-bit power of two >= N, walked until it lands in [0, N) (the paper
+ * names no shuffling method). */
+typedef enum {
+  DE_BASE_CLASSIC = 0,
+  DE_BASE_RANDOM = 1,
+  DE_BASE_OFFSET = 2,
+  DE_BASE_PERM = 3
+} de_base;
+
 /* Arithmetic of the rotated function's N x D x D product (ELLIPSOID_ROT only):
  *   DE_MM_FP64:   FP64 matrix cores, FP64 accumulation (dtype FP64)
  *   DE_MM_FP32:   FP32 matrix cores, FP32 accumulation (dtype FP32)
@@ -109,6 +128,13 @@ typedef struct {
                        or 64).
                        Indices, masks and trial rows do not depend on it;
                        fitness sums only change their rounding order. */
+  int32_t base;     /* de_base */
+  int32_t shuffle;  /* 1: shuffle the individuals at the start of every
+                       generation (Alg 2 line 5), 0: do not.  Applied as a
+                       relabelling: position k of generation g works on the
+                       individual stored in row pi_g(k) and writes its result
+                       back there, so rows never move; draws are addressed by
+                       position, trace rows by storage row. */
   double lo, hi;    /* initial population drawn uniformly from [lo, hi]^D, lo < hi */
   double olo, ohi;  /* shift o drawn uniformly from [olo, ohi]^D when shift == NULL */
   uint64_t seed;    /* Philox key */

@@ -22,6 +22,7 @@ EXP_IMPL = {"lane": 0, "job": 1, "scan": 2}
 FN = {"sphere": 0, "rastrigin": 1, "rosenbrock": 2, "ellipsoid_rot": 3, "ackley": 4, "griewank": 5}
 DTYPE = {"fp64": 0, "fp32": 1}
 MM = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+BASE = {"classic": 0, "random": 1, "offset": 2, "perm": 3}
 
 ABI_FUNCTIONS = ("de_workspace_size", "de_init", "de_generation", "de_evaluate", "de_best",
                  "de_get_state", "de_set_state", "de_trace", "de_profile", "de_profile_read",
@@ -38,7 +39,8 @@ class RunDesc(C.Structure):
     """Mirror of ``de_run_desc``."""
     _fields_ = [("N", C.c_int64), ("D", C.c_int64), ("F", C.c_double), ("CR", C.c_double),
                 ("xo", C.c_int32), ("fn", C.c_int32), ("dtype", C.c_int32), ("mm", C.c_int32),
-                ("exp_impl", C.c_int32), ("tpr", C.c_int32),
+                ("exp_impl", C.c_int32), ("tpr", C.c_int32), ("base", C.c_int32),
+                ("shuffle", C.c_int32),
                 ("lo", C.c_double), ("hi", C.c_double), ("olo", C.c_double), ("ohi", C.c_double),
                 ("seed", C.c_uint64), ("shift", C.c_void_p), ("rot", C.c_void_p)]
 
@@ -87,6 +89,7 @@ def _desc(run: dict, keep: list) -> RunDesc:
         xo=XO[run.get("xo", "bin")], fn=FN[run.get("fn", "sphere")],
         dtype=DTYPE[run.get("dtype", "fp64")], mm=MM[run.get("mm", "fp64")],
         exp_impl=EXP_IMPL[run.get("exp_impl", "lane")], tpr=int(run.get("tpr", 0)),
+        base=BASE[run.get("base", "classic")], shuffle=1 if run.get("shuffle") else 0,
         lo=float(run.get("lo", -100.0)), hi=float(run.get("hi", 100.0)),
         olo=float(run.get("olo", 0.0)), ohi=float(run.get("ohi", 0.0)),
         seed=int(run.get("seed", 0)),
@@ -113,8 +116,9 @@ class DE:
     """One handle over one or more runs (all runs step together).
 
     Each run is a dict with keys N, D, F, CR, xo, fn, dtype, mm, exp_impl,
-    lo, hi, olo, ohi, seed and optional device tensors shift (D values of the
-    run's dtype) and rot (D x D float64, rotated function only)."""
+    tpr, base, shuffle, lo, hi, olo, ohi, seed and optional device tensors
+    shift (D values of the run's dtype) and rot (D x D float64, rotated
+    function only)."""
 
     def __init__(self, runs: list[dict], device: str = "cuda:0", tune: bool = False):
         import torch

@@ -84,6 +84,73 @@ __device__ __forceinline__ void pick_indices(uint4 b, uint32_t N, uint32_t i, ui
   r2 += (r2 >= e2);
 }
 
+// Keyed pseudo-random permutation of [0, N) for generation g (the shuffle of
+// Alg 2 line 5 and Alg 5's base permutation): an eight-round balanced Feistel
+// network on m-bit integers (m even, 2^m >= N, m >= 2) whose round r mixes
+// the right half with K_r, word r%4 of Philox block r/4 (individual 0); the
+// image is walked through the permutation until it lands in [0, N).  A walk
+// ends at the latest when it returns to k, after at most 2^m < 4N steps.
+__device__ __forceinline__ uint32_t perm_mix(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t permute(const RunDev& P, uint32_t tag, uint32_t g, uint32_t N,
+                                            uint32_t k) {
+  uint32_t m = 2;
+  while ((1u << m) < N) m += 2;
+  const uint32_t h = m / 2, hmask = (1u << h) - 1u;
+  const uint4 a = draw(P, tag, g, 0, 0);
+  const uint4 b = draw(P, tag, g, 0, 1);
+  const uint32_t K[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  uint32_t x = k;
+  for (uint32_t step = 0; step < (1u << m); ++step) {
+    uint32_t L = x >> h, R = x & hmask;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t t = L ^ (perm_mix(R ^ K[r]) & hmask);
+      L = R;
+      R = t;
+    }
+    x = (L << h) | R;
+    if (x < N) break;
+  }
+  return x < N ? x : k;  // always x < N: the cycle through k returns within 2^m steps
+}
+
+// Storage row of position k in generation g (identity without the shuffle).
+__device__ __forceinline__ uint32_t row_of(const RunDev& P, uint32_t g, uint32_t k) {
+  return P.shuffle ? permute(P, TAG_SHUFFLE, g, static_cast<uint32_t>(P.N), k) : k;
+}
+
+// r0, r1, r2 (positions) of position k under the run's base scheme: the
+// classic distinct rule, or Alg 3 / 4 / 5 for r0 with Alg 6's offsets
+// o = 1 + randint(N - 1) for r1 = r0 + o1 and r2 = r1 + o2 (mod N).
+__device__ __forceinline__ void pick_scheme(const RunDev& P, uint32_t g, uint32_t k, uint32_t N,
+                                            uint32_t& r0, uint32_t& r1, uint32_t& r2) {
+  const uint4 b = draw(P, TAG_IDX, g, k, 0);
+  if (P.base == BASE_CLASSIC) {
+    pick_indices(b, N, k, r0, r1, r2);
+    return;
+  }
+  if (P.base == BASE_RANDOM) {
+    r0 = scale_index(b.x, N);
+  } else if (P.base == BASE_OFFSET) {
+    const uint32_t rg = 1 + scale_index(draw(P, TAG_OFFSET, g, 0, 0).x, N - 1);
+    r0 = k + rg >= N ? k + rg - N : k + rg;
+  } else {
+    r0 = permute(P, TAG_PERM, g, N, k);
+  }
+  const uint32_t o1 = 1 + scale_index(b.y, N - 1);
+  const uint32_t o2 = 1 + scale_index(b.z, N - 1);
+  r1 = r0 + o1 >= N ? r0 + o1 - N : r0 + o1;
+  r2 = r1 + o2 >= N ? r1 + o2 - N : r1 + o2;
+}
+
 // NEC run length from word w: the number of k in [1, D] with w < T[k], where
 // T[k] is the number of words whose uniform (w + 1/2) 2^-32 lies below
 // CR^(k-1) (the power as a running FP64 product).  T decreases in k, so the k

@@ -12,7 +12,9 @@ enum : int { FN_SPHERE = 0, FN_RASTRIGIN = 1, FN_ROSENBROCK = 2, FN_ELLIPSOID = 
              FN_GRIEWANK = 5, FN_ANY = -1, FN_NONE = -2 };
 enum : int { XO_BIN = 0, XO_EXP = 1, XO_NEC = 2, XO_ANY = -1 };
 enum : int { EXPI_LANE = 0, EXPI_JOB = 1, EXPI_SCAN = 2 };
-enum : uint32_t { TAG_INIT = 1, TAG_SHIFT = 2, TAG_IDX = 3, TAG_XO = 4, TAG_BIN = 5, TAG_EXP = 6 };
+enum : uint32_t { TAG_INIT = 1, TAG_SHIFT = 2, TAG_IDX = 3, TAG_XO = 4, TAG_BIN = 5, TAG_EXP = 6,
+                  TAG_OFFSET = 7, TAG_PERM = 8, TAG_SHUFFLE = 9 };
+enum : int { BASE_CLASSIC = 0, BASE_RANDOM = 1, BASE_OFFSET = 2, BASE_PERM = 3 };
 
 // Best so far of one run, as of generation g.  Kernels of a generation get
 // the handle's generation number as an argument (the host knows it without
@@ -43,6 +45,7 @@ struct alignas(64) RunDev {
   float Ff, pad0;
   uint32_t key0, key1, run_id;
   int32_t fn, xo, exp_impl, dtype, mm;
+  int32_t base, shuffle;  // base index scheme; per-generation shuffle on/off
   void* X[2];             // double-buffered populations, N x ld
   void* fit;              // N fitness values (dtype)
   uint8_t* flags;         // 2 x N: flags[(g & 1) * N + i] = buffer holding row i after gen g

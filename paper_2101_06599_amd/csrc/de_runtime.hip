@@ -126,6 +126,8 @@ de_status validate(const de_run_desc* runs, int32_t n_runs, std::string& msg) {
     if (d.xo < DE_XO_BIN || d.xo > DE_XO_NEC) return bad("unknown crossover");
     if (d.fn < DE_FN_SPHERE || d.fn > DE_FN_GRIEWANK) return bad("unknown function");
     if (d.exp_impl < DE_EXP_LANE || d.exp_impl > DE_EXP_SCAN) return bad("unknown exp_impl");
+    if (d.base < DE_BASE_CLASSIC || d.base > DE_BASE_PERM) return bad("unknown base scheme");
+    if (d.shuffle != 0 && d.shuffle != 1) return bad("shuffle must be 0 or 1");
     if (d.tpr != 0 && d.tpr != 64 && d.tpr != 256 && d.tpr != 512 && d.tpr != 1024)
       return bad("tpr must be 0, 64, 256, 512 or 1024");
     if (n_runs > 1 && d.tpr != 0 && d.tpr != 64) return bad("batched runs use tpr 0 or 64");
@@ -395,6 +397,7 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
     R.key1 = static_cast<uint32_t>(d.seed >> 32);
     R.run_id = static_cast<uint32_t>(r);
     R.fn = d.fn; R.xo = d.xo; R.exp_impl = d.exp_impl; R.dtype = d.dtype; R.mm = d.mm;
+    R.base = d.base; R.shuffle = d.shuffle;
     R.X[0] = ws + q.X0;
     R.X[1] = ws + q.X1;
     R.fit = ws + q.fit;

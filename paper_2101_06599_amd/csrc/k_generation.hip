@@ -210,11 +210,21 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   const uint32_t N = static_cast<uint32_t>(P.N);
   const int64_t ld = P.ld;
   DE_GLOBAL T* fit = gmut<T>(P.fit);
-  const T fold = FN != FN_NONE ? fit[i] : T(0);  // only row i's block writes it
+  // i is the row's position in Alg 2 (it addresses every draw); si is the
+  // storage row of the individual at that position (i itself unless the run
+  // shuffles, Alg 2 line 5).
+  const uint32_t si = __builtin_amdgcn_readfirstlane(row_of(P, R.g, i));
+  const T fold = FN != FN_NONE ? fit[si] : T(0);  // only row si's block writes it
 
-  // Alg 2 line 6 and the index draws of Alg 6: base r0, difference r1 - r2.
+  // Alg 2 line 6 and the index draws of Alg 6: base r0, difference r1 - r2,
+  // then the storage rows they name.
   uint32_t r0, r1, r2;
-  pick_indices(draw(P, TAG_IDX, R.g, i, 0), N, i, r0, r1, r2);
+  pick_scheme(P, R.g, i, N, r0, r1, r2);
+  if (P.shuffle) {
+    r0 = row_of(P, R.g, r0);
+    r1 = row_of(P, R.g, r1);
+    r2 = row_of(P, R.g, r2);
+  }
   // Alg 2 line 7: the crossover mask comes first (j_rand, and L for exp/NEC).
   const uint4 bx = draw(P, TAG_XO, R.g, i, 0);
   R.jr = scale_index(bx.x, R.D);
@@ -231,16 +241,16 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   r2 = __builtin_amdgcn_readfirstlane(r2);
   R.jr = __builtin_amdgcn_readfirstlane(R.jr);
   R.L = __builtin_amdgcn_readfirstlane(R.L);
-  const uint32_t ci = __builtin_amdgcn_readfirstlane(cur[i]);
+  const uint32_t ci = __builtin_amdgcn_readfirstlane(cur[si]);
   const uint32_t c0 = __builtin_amdgcn_readfirstlane(cur[r0]);
   const uint32_t c1 = __builtin_amdgcn_readfirstlane(cur[r1]);
   const uint32_t c2 = __builtin_amdgcn_readfirstlane(cur[r2]);
-  R.xi = gconst<T>(P.X[ci]) + static_cast<int64_t>(i) * ld;
+  R.xi = gconst<T>(P.X[ci]) + static_cast<int64_t>(si) * ld;
   R.x0 = gconst<T>(P.X[c0]) + static_cast<int64_t>(r0) * ld;
   R.x1 = gconst<T>(P.X[c1]) + static_cast<int64_t>(r1) * ld;
   R.x2 = gconst<T>(P.X[c2]) + static_cast<int64_t>(r2) * ld;
   R.o = gconst<T>(P.o);
-  R.dst = gmut<T>(P.X[ci ^ 1u]) + static_cast<int64_t>(i) * ld;
+  R.dst = gmut<T>(P.X[ci ^ 1u]) + static_cast<int64_t>(si) * ld;
 
   const uint32_t nchunk = (R.D + 3) >> 2;
   const bool tracing = P.tr_idx != nullptr || P.tr_mask != nullptr || P.tr_trial != nullptr;
@@ -378,30 +388,30 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   }
   if constexpr (FN != FN_NONE) {
     if (t == 0) {
-      nxt[i] = static_cast<uint8_t>(win ? ci ^ 1u : ci);
-      if (win) fit[i] = fu;
+      nxt[si] = static_cast<uint8_t>(win ? ci ^ 1u : ci);
+      if (win) fit[si] = fu;
       // deferred best-so-far: winners' new fitness, +inf for the others
-      gmut<T>(P.hist)[static_cast<int64_t>(gnew % kHist) * N + i] = win ? fu : Math<T>::inf();
+      gmut<T>(P.hist)[static_cast<int64_t>(gnew % kHist) * N + si] = win ? fu : Math<T>::inf();
     }
   }
 
   if (tracing) {
     const int64_t D = R.D;
     if (P.tr_idx && t == 0) {
-      int64_t* q = P.tr_idx + 6 * static_cast<int64_t>(i);
+      int64_t* q = P.tr_idx + 6 * static_cast<int64_t>(si);
       q[0] = r0; q[1] = r1; q[2] = r2; q[3] = R.jr;
       q[4] = R.xo == XO_BIN ? ctot : R.L;
       q[5] = (FN == FN_NONE) ? 0 : (win ? 1 : 0);
     }
-    if (P.tr_ftrial && t == 0 && FN != FN_NONE) static_cast<T*>(P.tr_ftrial)[i] = fu;
+    if (P.tr_ftrial && t == 0 && FN != FN_NONE) static_cast<T*>(P.tr_ftrial)[si] = fu;
     for (uint32_t c = t; c < nchunk; c += TPR) {
       T v[4];
       const uint32_t m = build_chunk(P, R, c, v);
       for (int e = 0; e < 4; ++e) {
         const uint32_t j = 4 * c + e;
         if (j >= R.D) break;
-        if (P.tr_mask) P.tr_mask[i * D + j] = static_cast<uint8_t>((m >> e) & 1u);
-        if (P.tr_trial) static_cast<T*>(P.tr_trial)[i * D + j] = v[e];
+        if (P.tr_mask) P.tr_mask[si * D + j] = static_cast<uint8_t>((m >> e) & 1u);
+        if (P.tr_trial) static_cast<T*>(P.tr_trial)[si * D + j] = v[e];
       }
     }
   }

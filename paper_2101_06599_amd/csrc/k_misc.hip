@@ -171,20 +171,26 @@ __global__ void __launch_bounds__(64) k_pexp_trial(const RunDev* __restrict__ ru
   const RunDev& P = runs[run];
   const uint32_t gnew = gen_value(gn);
   const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;  // position (draws)
   if (i >= N) return;
   const uint32_t g = run_gen(P, gnew);
+  const uint32_t si = row_of(P, g, i);                          // storage row
   const int64_t ld = P.ld;
   uint32_t r0, r1, r2;
-  pick_indices(draw(P, TAG_IDX, g, i, 0), N, i, r0, r1, r2);
+  pick_scheme(P, g, i, N, r0, r1, r2);
+  if (P.shuffle) {
+    r0 = row_of(P, g, r0);
+    r1 = row_of(P, g, r1);
+    r2 = row_of(P, g, r2);
+  }
   const uint32_t jr = scale_index(draw(P, TAG_XO, g, i, 0).x, D);
   const uint8_t* cur = P.flags + ((g - 1) & 1u) * static_cast<int64_t>(N);
-  const uint32_t ci = cur[i];
-  const T* xi = static_cast<const T*>(P.X[ci]) + static_cast<int64_t>(i) * ld;
+  const uint32_t ci = cur[si];
+  const T* xi = static_cast<const T*>(P.X[ci]) + static_cast<int64_t>(si) * ld;
   const T* x0 = static_cast<const T*>(P.X[cur[r0]]) + static_cast<int64_t>(r0) * ld;
   const T* x1 = static_cast<const T*>(P.X[cur[r1]]) + static_cast<int64_t>(r1) * ld;
   const T* x2 = static_cast<const T*>(P.X[cur[r2]]) + static_cast<int64_t>(r2) * ld;
-  T* u = static_cast<T*>(P.X[ci ^ 1u]) + static_cast<int64_t>(i) * ld;
+  T* u = static_cast<T*>(P.X[ci ^ 1u]) + static_cast<int64_t>(si) * ld;
   const T F = sizeof(T) == 4 ? static_cast<T>(P.Ff) : static_cast<T>(P.F);
   for (uint32_t j = 0; j < D; ++j) u[j] = xi[j];
   uint32_t j = jr, L = 0, e = 0;
@@ -199,15 +205,15 @@ __global__ void __launch_bounds__(64) k_pexp_trial(const RunDev* __restrict__ ru
     ++e;
   } while (more);
   if (P.tr_idx) {
-    int64_t* q = P.tr_idx + 6 * static_cast<int64_t>(i);
+    int64_t* q = P.tr_idx + 6 * static_cast<int64_t>(si);
     q[0] = r0; q[1] = r1; q[2] = r2; q[3] = jr; q[4] = L; q[5] = 0;
   }
   if (P.tr_trial)
-    for (uint32_t s = 0; s < D; ++s) static_cast<T*>(P.tr_trial)[static_cast<int64_t>(i) * D + s] = u[s];
+    for (uint32_t s = 0; s < D; ++s) static_cast<T*>(P.tr_trial)[static_cast<int64_t>(si) * D + s] = u[s];
   if (P.tr_mask)
     for (uint32_t s = 0; s < D; ++s) {
       const uint32_t off = s >= jr ? s - jr : s + D - jr;
-      P.tr_mask[static_cast<int64_t>(i) * D + s] = static_cast<uint8_t>(off < L);
+      P.tr_mask[static_cast<int64_t>(si) * D + s] = static_cast<uint8_t>(off < L);
     }
 }
 

@@ -12,7 +12,8 @@ import numpy as np
 import oracle
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x6": 1e-6, "bf16x3": 1e-4}
-ORACLE_KEYS = ("N", "D", "F", "CR", "xo", "fn", "dtype", "lo", "hi", "olo", "ohi", "seed")
+ORACLE_KEYS = ("N", "D", "F", "CR", "xo", "fn", "dtype", "lo", "hi", "olo", "ohi", "seed", "base",
+               "shuffle")
 
 
 def tol_of(cfg) -> float:

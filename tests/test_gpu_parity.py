@@ -214,6 +214,61 @@ def test_two_statistic_best_and_many_generations(name):
         assert (idx, g) == (ridx, rg)
 
 
+# ---- base index schemes (Alg 3-6) and the shuffle of Alg 2 line 5 ----------
+
+@pytest.mark.parametrize("shuffle", [False, True])
+@pytest.mark.parametrize("base", ["classic", "random", "offset", "perm"])
+@pytest.mark.parametrize("xo,dtype", [("bin", "fp64"), ("nec", "fp32")])
+def test_base_schemes_and_shuffle(base, shuffle, xo, dtype):
+    run_parity(rast(N=37, D=300, xo=xo, dtype=dtype, base=base, shuffle=shuffle), 4)
+
+
+@pytest.mark.parametrize("N", [4, 5, 17, 1000])
+def test_shuffle_and_permutation_small_and_ragged_populations(N):
+    run_parity(rast(N=N, D=40, xo="nec", base="perm", shuffle=True), 3)
+
+
+def test_shuffle_with_job_exp_and_rotated_paths():
+    run_parity(rast(N=30, D=200, xo="exp", exp_impl="job", base="offset", shuffle=True), 3)
+    rot = rotation(96, 5)
+    run_parity(ell("fp32", "fp32", D=96, N=50, xo="nec", base="perm", shuffle=True), 2, rot=rot)
+
+
+def test_batched_runs_with_mixed_schemes():
+    from paper_2101_06599_amd import synth
+    cfgs = synth.batch_table(n_runs=4, seed=3, max_D=200, max_N=50)
+    for c, (b, sh) in zip(cfgs, [("random", True), ("offset", False), ("perm", True),
+                                 ("classic", True)]):
+        c["base"], c["shuffle"] = b, sh
+    gpu = DE(cfgs)
+    refs = [oracle_run(c, run=r) for r, c in enumerate(cfgs)]
+    traces = [gpu.trace(r) for r in range(len(cfgs))]
+    for _ in range(3):
+        gpu.generation(1)
+        for r, c in enumerate(cfgs):
+            compare_generation(gpu, refs[r], c, run=r, trace=traces[r], stepped=True)
+
+
+def test_shuffled_full_size_sampled_rows():
+    from paper_2101_06599_amd import synth
+    cfg = dict(synth.RASTRIGIN_D1000, xo="nec", dtype="fp64", base="perm", shuffle=True)
+    sampled_rows(cfg, gens=3)
+
+
+def test_shuffled_graph_replay_matches_direct_launches():
+    cfgs = [rast(N=40, D=120, xo="bin", base="offset", shuffle=True)]
+    a, b = DE(cfgs), DE(cfgs)
+    b.graph(True)
+    for n in (3, 100, 64):
+        a.generation(n)
+        b.generation(n)
+    pa, fa, ga = a.state(0)
+    pb, fb, gb = b.state(0)
+    assert ga == gb == 167
+    assert np.array_equal(pa, pb) and np.array_equal(fa, fb)
+    assert a.best(0)[:3] == b.best(0)[:3]
+
+
 # ---- rotated ellipsoid on the matrix cores ---------------------------------
 
 def ell(mm, dtype, **kw):
