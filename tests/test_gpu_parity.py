@@ -333,6 +333,37 @@ def test_evaluate_matches_oracle(cfg):
         assert float(f0.cpu()[0]) == 0.0
 
 
+@pytest.mark.parametrize("fn", ["rastrigin", "ackley"])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_sin_squared_term_accuracy(fn, dtype):
+    """One-element rows across the whole argument range: the polynomial
+    sin^2(pi z) keeps each term within a few ulp (far inside the parity bar)."""
+    import torch
+    cfg = dict(N=8, D=1, F=0.5, CR=0.9, xo="nec", fn=fn, dtype=dtype, lo=-5.0, hi=5.0,
+               olo=-4.0, ohi=4.0, seed=2)
+    gpu = DE([cfg])
+    ref = oracle_run(cfg)
+    o = ref.shift()
+    rng = np.random.default_rng(5)
+    ints = np.arange(-6, 7, dtype=np.float64)
+    z = np.concatenate([rng.uniform(-6, 6, 20000), ints,
+                        *[ints + d for d in (1e-12, -1e-7, 0.25, 0.5, -0.5, 0.49999)],
+                        [1e4 + 0.3, -3e5 - 0.75, 1e-300, 0.0]])
+    dt = torch.float64 if dtype == "fp64" else torch.float32
+    Xd = torch.as_tensor((z + o[0])[:, None], dtype=dt, device="cuda:0")
+    Xr = Xd.cpu().numpy().astype(np.float64)
+    f = gpu.evaluate(0, Xd).cpu().numpy().astype(np.float64)
+    fr = oracle.fitness(fn, Xr, o)
+    phi = oracle.fitness_phi(fn, Xr, o)
+    # the argument x - o is rounded once on the GPU: allow its effect on top
+    # of a few ulp of the term
+    eps = 2.0 ** -52 if dtype == "fp64" else 2.0 ** -23
+    zz = np.abs(Xr[:, 0] - (o[0] if fn == "rastrigin" else 0.0))
+    bound = eps * (8 * phi + 80 * np.pi * zz * np.maximum(zz, 1.0))
+    bad = np.nonzero(np.abs(f - fr) > bound)[0]
+    assert bad.size == 0, (bad[:5], Xr[bad[:5], 0], f[bad[:5]], fr[bad[:5]])
+
+
 def test_evaluate_rotated():
     import torch
     D = 200
