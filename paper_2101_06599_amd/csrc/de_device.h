@@ -157,14 +157,24 @@ __device__ __forceinline__ void pick_scheme(const RunDev& P, uint32_t g, uint32_
 // that pass form a prefix: each lane of the wavefront tests one k, 64 at a
 // time (one coalesced load of the table), and the run length is the count.
 // Must be called by the whole wavefront with the same w.
-__device__ __forceinline__ uint32_t nec_length(const RunDev& P, uint32_t w) {
+// The table words the first step of nec_length needs (lane l: T[1 + l],
+// clamped to the last entry T[D + 1]), loaded on their own so that a caller
+// can issue the load early and overlap it with other memory traffic.
+__device__ __forceinline__ uint64_t nec_prefetch(const RunDev& P) {
+  const uint32_t D = static_cast<uint32_t>(P.D);
+  const uint32_t k = 1 + __lane_id();
+  return gconst<uint64_t>(P.T)[k <= D ? k : D + 1];
+}
+
+__device__ __forceinline__ uint32_t nec_length(const RunDev& P, uint32_t w, uint64_t t1) {
   const uint32_t D = static_cast<uint32_t>(P.D);
   if (P.inv_ln_cr == 0.0) return P.CR >= 1.0 ? D : 1u;
   const uint32_t lane = __lane_id();
   const uint64_t ww = w;
+  uint32_t L = static_cast<uint32_t>(__popcll(__ballot(1 + lane <= D && ww < t1)));
+  if (L < 64) return L;
   const DE_GLOBAL uint64_t* T = gconst<uint64_t>(P.T);
-  uint32_t L = 0;
-  for (uint32_t k0 = 1; k0 <= D; k0 += 64) {
+  for (uint32_t k0 = 65; k0 <= D; k0 += 64) {
     const uint32_t k = k0 + lane;
     const bool in = k <= D && ww < T[k];
     const uint32_t n = static_cast<uint32_t>(__popcll(__ballot(in)));
@@ -172,6 +182,10 @@ __device__ __forceinline__ uint32_t nec_length(const RunDev& P, uint32_t w) {
     if (n < 64) break;
   }
   return L;
+}
+
+__device__ __forceinline__ uint32_t nec_length(const RunDev& P, uint32_t w) {
+  return nec_length(P, w, nec_prefetch(P));
 }
 
 // Classic exponential crossover length (Alg 8), draws taken one at a time in

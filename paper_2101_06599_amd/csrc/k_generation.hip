@@ -225,26 +225,25 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
     r1 = row_of(P, R.g, r1);
     r2 = row_of(P, R.g, r2);
   }
-  // Alg 2 line 7: the crossover mask comes first (j_rand, and L for exp/NEC).
-  const uint4 bx = draw(P, TAG_XO, R.g, i, 0);
-  R.jr = scale_index(bx.x, R.D);
-  R.L = 0;
-  if (R.xo == XO_NEC) R.L = nec_length(P, bx.y);
-  else if (R.xo == XO_EXP) R.L = P.exp_impl == EXPI_SCAN ? exp_length_scan(P, R.g, i)
-                                                          : exp_length_serial(P, R.g, i);
-
   const DE_GLOBAL uint8_t* cur = gconst<uint8_t>(P.flags) + ((R.g - 1) & 1u) * static_cast<int64_t>(N);
   DE_GLOBAL uint8_t* nxt = gmut<uint8_t>(P.flags) + (R.g & 1u) * static_cast<int64_t>(N);
   // wave-uniform by construction; keep them (and the row pointers) scalar
   r0 = __builtin_amdgcn_readfirstlane(r0);
   r1 = __builtin_amdgcn_readfirstlane(r1);
   r2 = __builtin_amdgcn_readfirstlane(r2);
-  R.jr = __builtin_amdgcn_readfirstlane(R.jr);
-  R.L = __builtin_amdgcn_readfirstlane(R.L);
-  const uint32_t ci = __builtin_amdgcn_readfirstlane(cur[si]);
-  const uint32_t c0 = __builtin_amdgcn_readfirstlane(cur[r0]);
-  const uint32_t c1 = __builtin_amdgcn_readfirstlane(cur[r1]);
-  const uint32_t c2 = __builtin_amdgcn_readfirstlane(cur[r2]);
+  // The four buffer flags and the first NEC table words go out together; the
+  // parent row is requested as soon as its flag is back, and the run length
+  // is counted while that row is in flight.
+  const uint32_t fi = cur[si], f0 = cur[r0], f1 = cur[r1], f2 = cur[r2];
+  // Alg 2 line 7: the crossover mask comes first (j_rand, and L for exp/NEC).
+  const uint4 bx = draw(P, TAG_XO, R.g, i, 0);
+  R.jr = __builtin_amdgcn_readfirstlane(scale_index(bx.x, R.D));
+  uint64_t t1 = 0;
+  if (R.xo == XO_NEC) t1 = nec_prefetch(P);
+  const uint32_t ci = __builtin_amdgcn_readfirstlane(fi);
+  const uint32_t c0 = __builtin_amdgcn_readfirstlane(f0);
+  const uint32_t c1 = __builtin_amdgcn_readfirstlane(f1);
+  const uint32_t c2 = __builtin_amdgcn_readfirstlane(f2);
   R.xi = gconst<T>(P.X[ci]) + static_cast<int64_t>(si) * ld;
   R.x0 = gconst<T>(P.X[c0]) + static_cast<int64_t>(r0) * ld;
   R.x1 = gconst<T>(P.X[c1]) + static_cast<int64_t>(r1) * ld;
@@ -271,15 +270,20 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   const bool shifted = kShift && (FN != FN_ANY || fn != FN_SPHERE);
   V4<T> xs[MAXIT], os[MAXIT];
   if constexpr (kPrefetch) {
+    // Unconditional (lanes past the row reload its last chunk), so that the
+    // counted waits below can let these loads stay in flight.
 #pragma unroll
     for (int k = 0; k < MAXIT; ++k) {
-      const uint32_t c = k * TPR + t;
-      if (c < nchunk) {
-        xs[k] = load4(R.xi + 4 * c);
-        if (shifted) os[k] = load4(R.o + 4 * c);
-      }
+      const uint32_t c = min(k * TPR + t, nchunk - 1);
+      xs[k] = load4(R.xi + 4 * c);
+      if (shifted) os[k] = load4(R.o + 4 * c);
     }
   }
+  R.L = 0;
+  if (R.xo == XO_NEC) R.L = nec_length(P, bx.y, t1);
+  else if (R.xo == XO_EXP) R.L = P.exp_impl == EXPI_SCAN ? exp_length_scan(P, R.g, i)
+                                                          : exp_length_serial(P, R.g, i);
+  R.L = __builtin_amdgcn_readfirstlane(R.L);
   // Phase 2: mask, donors where the mask is set, trial and fitness terms.
 #pragma unroll
   for (int k = 0; k < MAXIT; ++k) {
