@@ -163,6 +163,28 @@ PAPER_TABLE1 = {(10, 100): (1.76, 6.99), (10, 1000): (1.18, 0.64), (10, 10000): 
                 (10000, 10000): (33.26, 39.14)}
 
 
+def time_masks(torch, de, run, out, reps):
+    """Seconds for masks of generations 1..reps of one run written to `out`:
+    the ABI call is made directly with prepared arguments, so the loop adds
+    little host time between the launches."""
+    import ctypes as C
+    h = de.DE([run])
+    s = torch.cuda.current_stream()
+    L, hh = de.lib(), h._h
+    ptr, st = C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)
+    L.de_masks(hh, 0, 1, ptr, st)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for g in range(1, reps + 1):
+        L.de_masks(hh, 0, g, ptr, st)
+    e1.record(s)
+    torch.cuda.synchronize()
+    h.close()
+    return e0.elapsed_time(e1) / 1e3
+
+
 def table1(torch, de, reps=100):
     """The paper's crossover-only grid: masks of 100 generations per Cr, summed
     over the five Cr values, with the masks written to device memory."""
@@ -171,23 +193,11 @@ def table1(torch, de, reps=100):
         row = {}
         for xo, paper in (("nec", p_nec), ("bin", p_bin), ("exp", None)):
             total = 0.0
+            out = torch.empty((N, D), dtype=torch.uint8, device="cuda:0")
             for CR in (0.2, 0.4, 0.6, 0.8, 1.0):
-                h = de.DE([dict(N=N, D=D, CR=CR, xo=xo, exp_impl="scan", fn="sphere",
-                                dtype="fp32", seed=0)])
-                out = torch.empty((N, D), dtype=torch.uint8, device="cuda:0")
-                h.masks(0, 1, out)
-                s = torch.cuda.current_stream()
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                torch.cuda.synchronize()
-                e0.record(s)
-                for g in range(1, reps + 1):
-                    h.masks(0, g, out)
-                e1.record(s)
-                torch.cuda.synchronize()
-                total += e0.elapsed_time(e1) / 1e3
-                h.close()
-                del out
+                total += time_masks(torch, de, dict(N=N, D=D, CR=CR, xo=xo, exp_impl="scan",
+                                                    fn="sphere", dtype="fp32", seed=0), out, reps)
+            del out
             row[xo] = {"total_s": total}
             if paper is not None:
                 row[xo].update(paper_cuda_s=paper, speedup_vs_paper=paper / total)
@@ -211,20 +221,9 @@ def fig456(torch, de, reps=100):
                 total = 0.0
                 out = torch.empty((N, D), dtype=torch.uint8, device="cuda:0")
                 for CR in (0.2, 0.4, 0.6, 0.8, 1.0):
-                    h = de.DE([dict(N=N, D=D, CR=CR, xo=xo, exp_impl=impl, fn="sphere",
-                                    dtype="fp32", seed=0)])
-                    h.masks(0, 1, out)
-                    s = torch.cuda.current_stream()
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    torch.cuda.synchronize()
-                    e0.record(s)
-                    for g in range(1, reps + 1):
-                        h.masks(0, g, out)
-                    e1.record(s)
-                    torch.cuda.synchronize()
-                    total += e0.elapsed_time(e1) / 1e3
-                    h.close()
+                    total += time_masks(torch, de, dict(N=N, D=D, CR=CR, xo=xo, exp_impl=impl,
+                                                        fn="sphere", dtype="fp32", seed=0),
+                                        out, reps)
                 row[name + "_s"] = total
                 del out
             row["p_exp_over_nec"] = row["p_exp_s"] / row["nec_s"]
