@@ -135,6 +135,14 @@ typedef struct {
                        individual stored in row pi_g(k) and writes its result
                        back there, so rows never move; draws are addressed by
                        position, trace rows by storage row. */
+  int32_t wb;       /* winners' write-back into the row's other buffer:
+                       0 = chosen from the population size (whole rows while
+                       one buffer of the handle fits in 48 MiB, else only the
+                       changed chunks), 1 = whole rows, 2 = only the chunks in
+                       which the two buffers differ (exp and NEC; binomial
+                       rows are always written whole).  Results do not depend
+                       on it. */
+  int32_t reserved; /* must be 0 */
   double lo, hi;    /* initial population drawn uniformly from [lo, hi]^D, lo < hi */
   double olo, ohi;  /* shift o drawn uniformly from [olo, ohi]^D when shift == NULL */
   uint64_t seed;    /* Philox key */

@@ -23,6 +23,7 @@ FN = {"sphere": 0, "rastrigin": 1, "rosenbrock": 2, "ellipsoid_rot": 3, "ackley"
 DTYPE = {"fp64": 0, "fp32": 1}
 MM = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 BASE = {"classic": 0, "random": 1, "offset": 2, "perm": 3}
+WB = {"auto": 0, "whole": 1, "partial": 2}
 
 ABI_FUNCTIONS = ("de_workspace_size", "de_init", "de_generation", "de_evaluate", "de_best",
                  "de_get_state", "de_set_state", "de_trace", "de_profile", "de_profile_read",
@@ -40,7 +41,7 @@ class RunDesc(C.Structure):
     _fields_ = [("N", C.c_int64), ("D", C.c_int64), ("F", C.c_double), ("CR", C.c_double),
                 ("xo", C.c_int32), ("fn", C.c_int32), ("dtype", C.c_int32), ("mm", C.c_int32),
                 ("exp_impl", C.c_int32), ("tpr", C.c_int32), ("base", C.c_int32),
-                ("shuffle", C.c_int32),
+                ("shuffle", C.c_int32), ("wb", C.c_int32), ("reserved", C.c_int32),
                 ("lo", C.c_double), ("hi", C.c_double), ("olo", C.c_double), ("ohi", C.c_double),
                 ("seed", C.c_uint64), ("shift", C.c_void_p), ("rot", C.c_void_p)]
 
@@ -90,6 +91,7 @@ def _desc(run: dict, keep: list) -> RunDesc:
         dtype=DTYPE[run.get("dtype", "fp64")], mm=MM[run.get("mm", "fp64")],
         exp_impl=EXP_IMPL[run.get("exp_impl", "lane")], tpr=int(run.get("tpr", 0)),
         base=BASE[run.get("base", "classic")], shuffle=1 if run.get("shuffle") else 0,
+        wb=WB[run.get("wb", "auto")],
         lo=float(run.get("lo", -100.0)), hi=float(run.get("hi", 100.0)),
         olo=float(run.get("olo", 0.0)), ohi=float(run.get("ohi", 0.0)),
         seed=int(run.get("seed", 0)),
@@ -116,7 +118,7 @@ class DE:
     """One handle over one or more runs (all runs step together).
 
     Each run is a dict with keys N, D, F, CR, xo, fn, dtype, mm, exp_impl,
-    tpr, base, shuffle, lo, hi, olo, ohi, seed and optional device tensors
+    tpr, base, shuffle, wb, lo, hi, olo, ohi, seed and optional device tensors
     shift (D values of the run's dtype) and rot (D x D float64, rotated
     function only)."""
 

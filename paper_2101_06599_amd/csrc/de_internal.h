@@ -32,6 +32,8 @@ struct alignas(32) BestState {
 // ring, and one pass over up to kHist generations updates the BestState.
 constexpr int kHist = 64;
 
+constexpr uint32_t kDirtyAll = 0xFFFFFFFFu;  // dirty run length meaning "the whole row"
+
 struct alignas(16) GenMin {
   double f;
   int64_t idx;
@@ -46,9 +48,15 @@ struct alignas(64) RunDev {
   uint32_t key0, key1, run_id;
   int32_t fn, xo, exp_impl, dtype, mm;
   int32_t base, shuffle;  // base index scheme; per-generation shuffle on/off
+  int32_t partial_wb;     // winners write only the chunks their buffers differ in
+  int32_t pad2;
   void* X[2];             // double-buffered populations, N x ld
   void* fit;              // N fitness values (dtype)
   uint8_t* flags;         // 2 x N: flags[(g & 1) * N + i] = buffer holding row i after gen g
+  uint4* dirty;           // N: (j0, L, partial, 0): row i's two buffers agree outside the
+                          // run of L elements from j0 (mod D), L = 0: equal, L >= D:
+                          // unknown; partial = 1 when winners write only that run and
+                          // their own (a copy of partial_wb next to the data it governs)
   const void* o;          // shift, ld values (dtype), zero padded
   const uint64_t* T;      // NEC thresholds, T[k] for k = 0..D+1
   BestState* best;
@@ -119,6 +127,9 @@ hipError_t launch_best_fp64(const RunDev* runs, const RunDev& h, int run, uint32
 hipError_t launch_normalize(const RunDev* runs, const RunDev& h, int run, uint32_t gcur,
                             hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
+// every row's dirty record := (0, L, run's write-back mode, 0)
+hipError_t launch_dirty_reset(const RunDev* runs, const RunDev& h, int run, uint32_t L,
+                              hipStream_t s);
 // crossover masks of generation g (run generation number), N x D bytes
 hipError_t launch_masks(const RunDev* runs, const RunDev& h, int run, uint32_t g, uint8_t* out,
                         hipStream_t s);

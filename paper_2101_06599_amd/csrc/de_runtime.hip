@@ -90,7 +90,7 @@ struct Layout {
   size_t total = 0;
   size_t runs_off = 0, best_off = 0, scratch_off = 0, rowmap_off = 0;
   struct Run {
-    size_t X0, X1, fit, flags, o, T, hist, mins, w, B[3], part, stage;
+    size_t X0, X1, fit, flags, dirty, o, T, hist, mins, w, B[3], part, stage;
     int64_t ld, ldk, ntile;
   };
   std::vector<Run> r;
@@ -128,6 +128,8 @@ de_status validate(const de_run_desc* runs, int32_t n_runs, std::string& msg) {
     if (d.exp_impl < DE_EXP_LANE || d.exp_impl > DE_EXP_SCAN) return bad("unknown exp_impl");
     if (d.base < DE_BASE_CLASSIC || d.base > DE_BASE_PERM) return bad("unknown base scheme");
     if (d.shuffle != 0 && d.shuffle != 1) return bad("shuffle must be 0 or 1");
+    if (d.wb < 0 || d.wb > 2) return bad("wb must be 0, 1 or 2");
+    if (d.reserved != 0) return bad("reserved must be 0");
     if (d.tpr != 0 && d.tpr != 64 && d.tpr != 256 && d.tpr != 512 && d.tpr != 1024)
       return bad("tpr must be 0, 64, 256, 512 or 1024");
     if (n_runs > 1 && d.tpr != 0 && d.tpr != 64) return bad("batched runs use tpr 0 or 64");
@@ -185,6 +187,7 @@ Layout layout(const de_run_desc* runs, int32_t n_runs) {
     q.X1 = bump(cur, pop);
     q.fit = bump(cur, s * d.N);
     q.flags = bump(cur, 2 * d.N);
+    q.dirty = bump(cur, sizeof(uint4) * d.N);
     q.o = bump(cur, s * q.ld);
     q.T = bump(cur, 8 * (d.D + 2));
     q.hist = bump(cur, s * d.N * de::kHist);
@@ -402,6 +405,7 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
     R.X[1] = ws + q.X1;
     R.fit = ws + q.fit;
     R.flags = reinterpret_cast<uint8_t*>(ws + q.flags);
+    R.dirty = reinterpret_cast<uint4*>(ws + q.dirty);
     R.o = ws + q.o;
     R.T = reinterpret_cast<const uint64_t*>(ws + q.T);
     R.best = h->best + r;
@@ -430,6 +434,13 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
     T[d.D + 1] = 0;
     h->tpr[r] = pick_tpr(d, h->batched);
   }
+  // Partial write-back pays once one population buffer of the handle outgrows
+  // the caches (measured crossover on MI355X: 30-80 MB; below, whole rows).
+  size_t pop_bytes = 0;
+  for (int r = 0; r < n_runs; ++r)
+    pop_bytes += static_cast<size_t>(esz(runs[r].dtype)) * runs[r].N * L.r[r].ld;
+  for (int r = 0; r < n_runs; ++r)
+    h->host[r].partial_wb = runs[r].wb == 2 || (runs[r].wb == 0 && pop_bytes > (size_t(48) << 20));
   h->single_kernel = true;
   for (int r = 0; r < n_runs; ++r)
     if (runs[r].fn == DE_FN_ELLIPSOID_ROT || (runs[r].xo == DE_XO_EXP && runs[r].exp_impl == DE_EXP_JOB))
@@ -631,6 +642,8 @@ de_status de_set_state(de_handle* h, int32_t run, const void* pop_host, const vo
                                hipMemcpyHostToDevice, s));
   HIPCHECK(h, hipMemcpyAsync(R.fit, fit_host, e * R.N, hipMemcpyHostToDevice, s));
   HIPCHECK(h, de::launch_fill_u8(R.flags, 2 * R.N, 0, s));
+  // buffer 1 no longer matches buffer 0 anywhere in particular
+  HIPCHECK(h, de::launch_dirty_reset(h->dev_runs, R, run, de::kDirtyAll, s));
   HIPCHECK(h, hipMemcpyAsync(h->best + run, &B, sizeof B, hipMemcpyHostToDevice, s));
   HIPCHECK(h, upload_run(h, run, s));
   HIPCHECK(h, hipStreamSynchronize(s));

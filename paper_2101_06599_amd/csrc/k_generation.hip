@@ -55,6 +55,20 @@ struct RowCtx {
   int xo;
 };
 
+// Whether chunk c holds an element of the run of L elements from j0 (mod D);
+// L = 0 is the empty run, L >= D the whole row.
+__device__ __forceinline__ bool run_touches(uint32_t j0, uint32_t L, uint32_t c, uint32_t D) {
+  if (L >= D) return true;
+  bool hit = false;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const uint32_t j = 4 * c + v;
+    const uint32_t off = j >= j0 ? j - j0 : j + D - j0;
+    hit |= j < D && off < L;
+  }
+  return hit;
+}
+
 // Chunk c of the trial row: mask bits (bit v = element 4c+v crosses) and the
 // four trial values.  Elements at or beyond D keep the parent's (padding).
 template <typename T>
@@ -215,6 +229,10 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   // shuffles, Alg 2 line 5).
   const uint32_t si = __builtin_amdgcn_readfirstlane(row_of(P, R.g, i));
   const T fold = FN != FN_NONE ? fit[si] : T(0);  // only row si's block writes it
+  // The row's dirty record (only row si's block writes it): lane l holds its
+  // word l % 4.  A vector load, so its wait is counted and comes only at the
+  // write-back (a scalar load would hold up every later scalar-cache wait).
+  const uint32_t dword = gconst<uint32_t>(P.dirty)[4 * static_cast<int64_t>(si) + (__lane_id() & 3u)];
 
   // Alg 2 line 6 and the index draws of Alg 6: base r0, difference r1 - r2,
   // then the storage rows they name.
@@ -379,16 +397,42 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
     win = fu < fold;
   }
   if (win) {
+    // Write-back into the other buffer.  It already equals the parent outside
+    // the run in the row's record, and the trial equals the parent outside its
+    // mask, so in partial mode only chunks in either are written; the buffers
+    // then differ exactly where the mask was set.  Binomial masks are
+    // scattered, and small populations (which live in the caches and read a
+    // freshly written row fastest) use whole mode: whole rows are written.
+    const uint32_t pj = __builtin_amdgcn_readlane(dword, 0);
+    const uint32_t pl = __builtin_amdgcn_readlane(dword, 1);
+    const uint32_t pw = __builtin_amdgcn_readlane(dword, 2);
+    const bool whole = R.xo == XO_BIN || pw == 0 || pl >= R.D;
+    if (whole) {
 #pragma unroll
-    for (int k = 0; k < MAXIT; ++k) {
-      const uint32_t c = k * TPR + t;
-      if (c < nchunk) store4(R.dst + 4 * c, u[k]);
+      for (int k = 0; k < MAXIT; ++k) {
+        const uint32_t c = k * TPR + t;
+        if (c < nchunk) store4(R.dst + 4 * c, u[k]);
+      }
+      for (uint32_t c = MAXIT * TPR + t; c < nchunk; c += TPR) {
+        T v[4];
+        build_chunk(P, R, c, v);
+        store4(R.dst + 4 * c, v);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < MAXIT; ++k) {
+        const uint32_t c = k * TPR + t;
+        if (c < nchunk && (mb[k] != 0 || run_touches(pj, pl, c, R.D))) store4(R.dst + 4 * c, u[k]);
+      }
+      for (uint32_t c = MAXIT * TPR + t; c < nchunk; c += TPR) {
+        T v[4];
+        const uint32_t m = build_chunk(P, R, c, v);
+        if (m != 0 || run_touches(pj, pl, c, R.D)) store4(R.dst + 4 * c, v);
+      }
     }
-    for (uint32_t c = MAXIT * TPR + t; c < nchunk; c += TPR) {
-      T v[4];
-      build_chunk(P, R, c, v);
-      store4(R.dst + 4 * c, v);
-    }
+    if (t == 0 && pw != 0)
+      gmut<uint4>(P.dirty)[si] = R.xo == XO_BIN ? make_uint4(0u, kDirtyAll, pw, 0u)
+                                                : make_uint4(R.jr, R.L, pw, 0u);
   }
   if constexpr (FN != FN_NONE) {
     if (t == 0) {

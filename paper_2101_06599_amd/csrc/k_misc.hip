@@ -40,9 +40,11 @@ __global__ void k_init(const RunDev* __restrict__ runs, int32_t run, double lo, 
     const T v = j < D ? init_value<T>(P, TAG_INIT, static_cast<uint32_t>(i),
                                       static_cast<uint32_t>(j), lo, hi)
                       : T(0);
+    // both buffers start equal, so a row's first write-back is partial too
     static_cast<T*>(P.X[0])[e] = v;
-    static_cast<T*>(P.X[1])[e] = T(0);
+    static_cast<T*>(P.X[1])[e] = v;
   }
+  if (e < N) P.dirty[e] = make_uint4(0u, 0u, static_cast<uint32_t>(P.partial_wb), 0u);
   if (e < ld) {
     T ov = T(0);
     if (e < D) {
@@ -192,6 +194,8 @@ __global__ void __launch_bounds__(64) k_pexp_trial(const RunDev* __restrict__ ru
   const T* x2 = static_cast<const T*>(P.X[cur[r2]]) + static_cast<int64_t>(r2) * ld;
   T* u = static_cast<T*>(P.X[ci ^ 1u]) + static_cast<int64_t>(si) * ld;
   const T F = sizeof(T) == 4 ? static_cast<T>(P.Ff) : static_cast<T>(P.F);
+  // u becomes the whole trial; whichever way selection goes, the two buffers
+  // then differ only inside this run
   for (uint32_t j = 0; j < D; ++j) u[j] = xi[j];
   uint32_t j = jr, L = 0, e = 0;
   uint4 b = make_uint4(0, 0, 0, 0);
@@ -204,6 +208,7 @@ __global__ void __launch_bounds__(64) k_pexp_trial(const RunDev* __restrict__ ru
     more = static_cast<uint64_t>(word_of(b, e & 3u)) < P.thr && L < D;
     ++e;
   } while (more);
+  P.dirty[si] = make_uint4(jr, L, static_cast<uint32_t>(P.partial_wb), 0u);
   if (P.tr_idx) {
     int64_t* q = P.tr_idx + 6 * static_cast<int64_t>(si);
     q[0] = r0; q[1] = r1; q[2] = r2; q[3] = jr; q[4] = L; q[5] = 0;
@@ -394,6 +399,12 @@ __global__ void k_gen_base(uint32_t* base, uint32_t v, int add) {
   if (threadIdx.x == 0) *base = add ? *base + v : v;
 }
 
+__global__ void k_dirty_reset(const RunDev* __restrict__ runs, int32_t run, uint32_t L) {
+  const RunDev& P = runs[run];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < P.N) P.dirty[i] = make_uint4(0u, L, static_cast<uint32_t>(P.partial_wb), 0u);
+}
+
 __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e < n) p[e] = v;
@@ -402,6 +413,12 @@ __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
 // ---- launchers ---------------------------------------------------------------
 
 static inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
+
+hipError_t launch_dirty_reset(const RunDev* runs, const RunDev& h, int run, uint32_t L,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_dirty_reset, dim3(nblk(h.N, 256)), dim3(256), 0, s, runs, run, L);
+  return hipGetLastError();
+}
 
 hipError_t launch_init_impl(const RunDev* runs, const RunDev& h, int run, double lo, double hi,
                             double olo, double ohi, const void* shift, hipStream_t s) {

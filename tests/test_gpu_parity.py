@@ -269,6 +269,51 @@ def test_shuffled_graph_replay_matches_direct_launches():
     assert a.best(0)[:3] == b.best(0)[:3]
 
 
+# ---- partial write-back: winners write only where the buffers differ -------
+
+@pytest.mark.parametrize("xo,impl,dtype", [("nec", "lane", "fp64"), ("exp", "scan", "fp32"),
+                                           ("exp", "job", "fp64"), ("bin", "lane", "fp32")])
+def test_partial_write_back_many_generations(xo, impl, dtype):
+    # CR 0.6 keeps runs short, so most rows are written partially
+    run_parity(rast(N=40, D=257, CR=0.6, xo=xo, exp_impl=impl, dtype=dtype, wb="partial"), 30)
+
+
+def test_partial_write_back_paths():
+    # rotated trial-only kernel, the shuffle, a wide row with the register-cache
+    # overflow, and a resume (set_state leaves the buffers unrelated)
+    rot = rotation(96, 4)
+    run_parity(ell("fp32", "fp32", D=96, N=50, xo="nec", wb="partial"), 6, rot=rot)
+    run_parity(rast(N=24, D=300, xo="nec", base="perm", shuffle=True, wb="partial"), 8)
+    run_parity(rosen(D=4500, N=8, xo="nec", CR=0.99, wb="partial", tpr=64), 4)
+    cfg = rast(N=30, D=200, CR=0.7, xo="nec", wb="partial")
+    gpu, ref, _ = run_parity(cfg, 5)
+    pop, fit, g = ref.state()
+    bf, bi, bg, _ = ref.best()
+    gpu.set_state(0, pop, fit, g, bf, bi, bg)
+    trace = gpu.trace(0)
+    for _ in range(10):
+        compare_generation(gpu, ref, cfg, trace=trace)
+
+
+@pytest.mark.parametrize("cfgs", ["single", "batched"])
+def test_write_back_modes_agree(cfgs):
+    from paper_2101_06599_amd import synth
+    if cfgs == "single":
+        base = [rast(N=64, D=500, CR=0.8, xo="nec", dtype="fp32")]
+    else:
+        base = synth.batch_table(n_runs=5, seed=4, max_D=300, max_N=40)
+    outs = []
+    for wb in ("whole", "partial", "auto"):
+        gpu = DE([dict(c, wb=wb) for c in base])
+        gpu.generation(150)
+        outs.append([gpu.state(r) for r in range(len(base))] + [gpu.best(r)[:3] for r in range(len(base))])
+        gpu.close()
+    for o in outs[1:]:
+        for a, b in zip(o[:len(base)], outs[0][:len(base)]):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+        assert o[len(base):] == outs[0][len(base):]
+
+
 # ---- rotated ellipsoid on the matrix cores ---------------------------------
 
 def ell(mm, dtype, **kw):
