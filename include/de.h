@@ -124,7 +124,8 @@ typedef struct {
   int32_t mm;       /* de_matmul, ELLIPSOID_ROT only (ignored otherwise) */
   int32_t exp_impl; /* de_exp_impl, DE_XO_EXP only */
   int32_t tpr;      /* lanes per individual in the generation kernel: 0 = chosen
-                       from D and N; 64, 256, 512 or 1024 forces it (batched: 0
+                       from D, N and dtype; 64, 128, 256, 512 or 1024 forces
+                       it (batched: 0
                        or 64).
                        Indices, masks and trial rows do not depend on it;
                        fitness sums only change their rounding order. */

@@ -130,8 +130,8 @@ de_status validate(const de_run_desc* runs, int32_t n_runs, std::string& msg) {
     if (d.shuffle != 0 && d.shuffle != 1) return bad("shuffle must be 0 or 1");
     if (d.wb < 0 || d.wb > 2) return bad("wb must be 0, 1 or 2");
     if (d.reserved != 0) return bad("reserved must be 0");
-    if (d.tpr != 0 && d.tpr != 64 && d.tpr != 256 && d.tpr != 512 && d.tpr != 1024)
-      return bad("tpr must be 0, 64, 256, 512 or 1024");
+    if (d.tpr != 0 && d.tpr != 64 && d.tpr != 128 && d.tpr != 256 && d.tpr != 512 && d.tpr != 1024)
+      return bad("tpr must be 0, 64, 128, 256, 512 or 1024");
     if (n_runs > 1 && d.tpr != 0 && d.tpr != 64) return bad("batched runs use tpr 0 or 64");
     if (is_shifted(d.fn) && !d.shift &&
         !(std::isfinite(d.olo) && std::isfinite(d.ohi) && d.olo <= d.ohi))
@@ -214,13 +214,21 @@ Layout layout(const de_run_desc* runs, int32_t n_runs) {
 int pick_tpr(const de_run_desc& d, bool batched) {
   if (batched) return 64;
   if (d.tpr != 0) return d.tpr;
-  // measured defaults: a row held in registers by as few lanes as fit ...
+  // Measured defaults (MI355X): a row held in registers by as few lanes as
+  // fit; rows of up to 1024 elements take 128 lanes (2 chunks each) where the
+  // shorter per-lane chain pays for the second wavefront: FP64 runs of the
+  // ALU-heavy functions (Rastrigin NEC 8.5 vs 9.0 us at N = 2048) and
+  // binomial runs (11.4 vs 12.2 us); FP32 exp/NEC (6.4 vs 6.7 us) and the
+  // sphere (6.6 vs 7.1 us) stay at 64 ...
   const int64_t nchunk = (d.D + 3) / 4;
   int t = nchunk <= 64 * 4 ? 64 : nchunk <= 256 * 4 ? 256 : nchunk <= 512 * 5 ? 512 : 1024;
-  // ... widened while the run has fewer wavefronts than the chip has SIMDs
+  const bool alu_heavy = d.dtype == DE_FP64 && d.fn != DE_FN_SPHERE;
+  if (t == 64 && nchunk > 64 && (alu_heavy || d.xo == DE_XO_BIN)) t = 128;
+  // ... widened while the run has fewer wavefronts than half the chip's SIMDs
   // (256 CUs x 4) and every lane still has more than one chunk: small
-  // populations then finish each row in fewer dependent steps.
-  while (t < 1024 && nchunk > t && d.N * (t / 64) < 1024) t = t == 64 ? 256 : 2 * t;
+  // populations then finish each row in fewer dependent steps (Ackley
+  // D = 1000 N = 500: 5.8 us at 128 lanes, 6.1 at 256, 8.4 at 64).
+  while (t < 1024 && nchunk > t && d.N * (t / 64) < 512) t = t == 64 ? 128 : 2 * t;
   return t;
 }
 

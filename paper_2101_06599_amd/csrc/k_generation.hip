@@ -176,11 +176,13 @@ template <int TPR> struct Shape {
   static constexpr int RPB = BS / TPR;               // rows per block
   static constexpr int NW = TPR / 64;                // wavefronts per row
   // chunks of 4 elements held in registers per thread: D <= 16 * TPR (20 * 512
-  // for 512-wide rows) stays in registers between evaluation and write-back
-  static constexpr int MAXIT = TPR == 512 ? 5 : 4;
-  // 64-lane rows issue every cached chunk's parent loads before using any
-  // (more loads in flight per wave); wide rows would lose occupancy to it
-  static constexpr bool PREFETCH = TPR == 64;
+  // for 512-wide rows, 8 * 128 for 128-wide rows) stays in registers between
+  // evaluation and write-back
+  static constexpr int MAXIT = TPR == 512 ? 5 : TPR == 128 ? 2 : 4;
+  // 64- and 128-lane rows issue every cached chunk's parent loads before
+  // using any (more loads in flight per wave); wider rows would lose
+  // occupancy to it
+  static constexpr bool PREFETCH = TPR <= 128;
 };
 
 // FN: a fixed function, FN_ANY (taken from the run record) or FN_NONE (build
@@ -485,6 +487,7 @@ template <typename T, int FN, int XO>
 static hipError_t go_tpr(const GenLaunch& L, bool batched) {
   switch (L.tpr) {
     case 64: return go<T, FN, XO, 64>(L, batched);
+    case 128: return go<T, FN, XO, 128>(L, batched);
     case 256: return go<T, FN, XO, 256>(L, batched);
     case 512: return go<T, FN, XO, 512>(L, batched);
     case 1024: return go<T, FN, XO, 1024>(L, batched);

@@ -1,6 +1,6 @@
 """Launch-shape autotuner for the generation kernel.
 
-The lanes given to one individual (`tpr`: 64, 256, 512 or 1024) trade the
+The lanes given to one individual (`tpr`: 64, 128, 256, 512 or 1024) trade the
 number of rows in flight against per-row work; the library's default follows
 D and N.  tune_tpr() times every candidate on a scratch handle of the same
 shape (results never depend on tpr) and keeps the fastest per device and run
@@ -10,7 +10,7 @@ from __future__ import annotations
 import json
 import os
 
-CANDIDATES = (64, 256, 512, 1024)
+CANDIDATES = (64, 128, 256, 512, 1024)
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 SHAPE_KEYS = ("dtype", "fn", "xo", "exp_impl", "mm", "N", "D")
 

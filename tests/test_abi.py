@@ -44,7 +44,7 @@ def test_workspace_size_and_validation(lib):
     big = de.workspace_size([good(N=2048, D=1000, fn="rastrigin", olo=-4, ohi=4)])
     assert big >= 2 * 2048 * 1024 * 8  # two padded FP64 population buffers
     bad = [good(N=3), good(D=0), good(CR=1.5), good(CR=float("nan")), good(F=-1.0),
-           good(F=float("inf")), good(lo=1.0, hi=1.0), good(N=1 << 21), good(tpr=128)]
+           good(F=float("inf")), good(lo=1.0, hi=1.0), good(N=1 << 21), good(tpr=96)]
     for field, v in (("base", 4), ("base", -1), ("shuffle", 2), ("wb", 3), ("reserved", 1)):
         keep0: list = []
         d0 = de._desc(good(), keep0)

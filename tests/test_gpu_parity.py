@@ -120,7 +120,7 @@ def test_rosenbrock_d1000(dtype):
 @pytest.mark.parametrize("cfg", [rast(N=40, D=999, xo="bin"), rosen(D=1001, N=20, xo="nec")])
 def test_row_width_invariance(cfg):
     outs = []
-    for tpr in (64, 256, 512, 1024):
+    for tpr in (64, 128, 256, 512, 1024):
         gpu = DE([dict(cfg, tpr=tpr)])
         tr = gpu.trace(0)
         gpu.generation(1)
@@ -162,7 +162,7 @@ def test_two_statistic_row_shapes(name, D):
 def test_two_statistic_row_width_invariance(name):
     cfg = table2(name, D=1501, N=24, xo="nec")
     outs = []
-    for tpr in (64, 256, 512, 1024):
+    for tpr in (64, 128, 256, 512, 1024):
         gpu = DE([dict(cfg, tpr=tpr)])
         tr = gpu.trace(0)
         gpu.generation(1)
@@ -555,7 +555,7 @@ def test_autotuned_row_width_gives_same_generations():
     from paper_2101_06599_amd.tune import tune_tpr
     cfg = rast(N=48, D=700, xo="nec", dtype="fp32")
     best, table = tune_tpr(cfg, gens=8, use_cache=False)
-    assert best in (64, 256, 512, 1024) and set(table) == {64, 256, 512, 1024}
+    assert best in (64, 128, 256, 512, 1024) and set(table) == {64, 128, 256, 512, 1024}
     assert all(v > 0 for v in table.values())
     a, b = DE([cfg]), DE([dict(cfg, tpr=best)])
     a.generation(20)
