@@ -71,6 +71,7 @@ struct alignas(64) RunDev {
   void* part;             // N x ntile partial sums (dtype)
   int32_t ntile, pad1;
   void* stage;            // N x ld staging rows (rotated evaluate)
+  void* apc;              // split-bf16 modes: pieces of U - o, P x N x ldk bf16
   // trace (tests)
   int64_t* tr_idx;
   uint8_t* tr_mask;

@@ -90,7 +90,7 @@ struct Layout {
   size_t total = 0;
   size_t runs_off = 0, best_off = 0, scratch_off = 0, rowmap_off = 0;
   struct Run {
-    size_t X0, X1, fit, flags, dirty, o, T, hist, mins, w, B[3], part, stage;
+    size_t X0, X1, fit, flags, dirty, o, T, hist, mins, w, B[3], part, stage, apc;
     int64_t ld, ldk, ntile;
   };
   std::vector<Run> r;
@@ -194,7 +194,7 @@ Layout layout(const de_run_desc* runs, int32_t n_runs) {
     q.mins = bump(cur, sizeof(de::GenMin) * de::kHist);
     q.ldk = 0;
     q.ntile = 0;
-    q.w = q.part = q.stage = 0;
+    q.w = q.part = q.stage = q.apc = 0;
     q.B[0] = q.B[1] = q.B[2] = 0;
     if (d.fn == DE_FN_ELLIPSOID_ROT) {
       q.ldk = up64(d.D, 32);
@@ -205,6 +205,8 @@ Layout layout(const de_run_desc* runs, int32_t n_runs) {
         q.B[p] = bump(cur, static_cast<size_t>(mm_elem(d.mm)) * rows_pad * q.ldk);
       q.part = bump(cur, s * d.N * q.ntile);
       q.stage = bump(cur, pop);
+      if (d.mm == DE_MM_BF16X3 || d.mm == DE_MM_BF16X6)
+        q.apc = bump(cur, static_cast<size_t>(2) * mm_pieces(d.mm) * d.N * q.ldk);
     }
   }
   L.total = cur;
@@ -428,6 +430,7 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
       R.part = ws + q.part;
       R.ntile = static_cast<int32_t>(q.ntile);
       R.stage = ws + q.stage;
+      R.apc = q.apc ? ws + q.apc : nullptr;
     }
     // NEC thresholds: T[k] = #words below CR^(k-1), the power taken as a
     // running FP64 product; T[D+1] = 0 ends the search.

@@ -3,11 +3,13 @@
 // product with both operands contiguous along the contraction index.
 //
 // One kernel does the product on the matrix cores with the shift subtraction
-// (and, for the split-bf16 modes, the hi/mid/lo split of U - o) fused into the
-// A-tile load, and the weighted square sum fused into the epilogue, so Z is
-// never stored: each block writes one partial sum per row for its 128 output
-// columns.  A second kernel adds the partials of a row in a fixed order and
-// performs greedy selection.
+// fused into the A-tile load (FP32/FP64) and the weighted square sum fused
+// into the epilogue, so Z is never stored: each block writes one partial sum
+// per row for its 128 output columns.  A second kernel adds the partials of a
+// row in a fixed order and performs greedy selection.  For the split-bf16
+// modes a pass before the product writes the hi/mid/lo pieces of U - o once
+// (the product reads every A row once per column tile, 16 times at D = 2048,
+// and splitting inside it cost matrix-core time).
 //
 // Modes: FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_16x16x4), and bf16
 // splits of both operands into 2 or 3 pieces whose 3 or 6 leading cross
@@ -81,6 +83,32 @@ __device__ __forceinline__ void copy16(V* __restrict__ dst, const V* __restrict_
     reinterpret_cast<uint4*>(dst)[q] = reinterpret_cast<const uint4*>(src)[q];
 }
 
+// Pieces of A = U - o for the split-bf16 modes, zero past D, interleaved by
+// groups of 8 k: the P pieces of group g of row i are 8 consecutive values
+// each at apc + ((i * ldk / 8 + g) * P + p) * 8, so a thread of the product
+// reads its segment's pieces in one contiguous run.  One thread per group.
+template <int P>
+__global__ void __launch_bounds__(256) k_rot_split(const RunDev* __restrict__ runs, int32_t run,
+                                                  int src, GenNo ghn, int64_t rows) {
+  const RunDev& Pr = runs[run];
+  const int64_t ldk = Pr.ldk, D = Pr.D;
+  const int64_t e = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * 8;
+  if (e >= rows * ldk) return;
+  const int64_t i = e / ldk, k0 = e % ldk;  // ldk is a multiple of 32
+  const float* a = a_row<float>(Pr, src, gen_value(ghn), i);
+  const float* o = static_cast<const float*>(Pr.o);
+  __attribute__((aligned(16))) __bf16 h[8], m[8], l[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int64_t k = k0 + v;
+    split3(k < D ? a[k] - o[k] : 0.0f, h[v], m[v], l[v]);
+  }
+  __bf16* out = static_cast<__bf16*>(Pr.apc) + (i * (ldk / 8) + k0 / 8) * P * 8;
+  copy16<__bf16, 8>(out, h);
+  copy16<__bf16, 8>(out + 8, m);
+  if constexpr (P == 3) copy16<__bf16, 8>(out + 16, l);
+}
+
 // The product for one 128x128 (FP64: 64x64) tile of Z.  The next K slice is
 // fetched into registers while the matrix cores work on the current one from
 // LDS; the slice is then split (bf16 modes) and written into the other LDS
@@ -124,38 +152,66 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   const int a_r = tid / A_TPR, a_k = (tid % A_TPR) * A_SEG;
   const int b_r = tid / B_TPR, b_k = (tid % B_TPR) * B_SEG;
   const int64_t ai = min(row0 + a_r, rows - 1);
-  const T* arow = a_row<T>(Pr, src, gh, ai) + a_k;
+  // FP32/FP64: the row itself and the shift; bf16 modes: the row's pieces
+  const T* arow = P == 1 ? a_row<T>(Pr, src, gh, ai) + a_k : nullptr;
   const T* orow = static_cast<const T*>(Pr.o) + a_k;
+  const __bf16* aprow = P == 1 ? nullptr
+                               : static_cast<const __bf16*>(Pr.apc) + (ai * (ldk / 8) + a_k / 8) * P * 8;
   const LT* brow[P];
 #pragma unroll
   for (int p = 0; p < P; ++p)  // rows of M pieces are padded to a multiple of 128
     brow[p] = static_cast<const LT*>(Pr.B[p]) + (col0 + b_r) * ldk + b_k;
 
-  __attribute__((aligned(16))) T ra[A_SEG], ro[A_SEG];
-  __attribute__((aligned(16))) LT rb[P][B_SEG];
-  auto fetch = [&](int64_t k0) {
-    copy16<T, A_SEG>(ra, arow + k0);
-    copy16<T, A_SEG>(ro, orow + k0);  // padding columns hold zeros on both sides
-#pragma unroll
-    for (int p = 0; p < P; ++p) copy16<LT, B_SEG>(rb[p], brow[p] + k0);
-  };
-  auto stash = [&](int buf) {
-    if constexpr (P == 1) {
-      __attribute__((aligned(16))) T a[A_SEG];
-#pragma unroll
-      for (int e = 0; e < A_SEG; ++e) a[e] = ra[e] - ro[e];
-      copy16<T, A_SEG>(&As[buf][0][a_r][a_k], a);
-    } else {
-      __attribute__((aligned(16))) __bf16 h[A_SEG], m[A_SEG], l[A_SEG];
-#pragma unroll
-      for (int e = 0; e < A_SEG; ++e) split3(ra[e] - ro[e], h[e], m[e], l[e]);
-      copy16<__bf16, A_SEG>(&As[buf][0][a_r][a_k], h);
-      copy16<__bf16, A_SEG>(&As[buf][1][a_r][a_k], m);
-      if constexpr (P == 3) copy16<__bf16, A_SEG>(&As[buf][2][a_r][a_k], l);
-    }
-#pragma unroll
-    for (int p = 0; p < P; ++p) copy16<LT, B_SEG>(&Bs[buf][p][b_r][b_k], rb[p]);
-  };
+  // The next K slice, held as 16-byte vectors only (element access through
+  // casts of local arrays would put them in scratch memory).
+  constexpr int AV = (P == 1 ? A_SEG * static_cast<int>(sizeof(T)) : A_SEG * 2) / 16;
+  constexpr int BV = B_SEG * static_cast<int>(sizeof(LT)) / 16;
+  constexpr int AE = 16 / static_cast<int>(sizeof(T));   // A elements per vector (P == 1)
+  constexpr int BE = 16 / static_cast<int>(sizeof(LT));  // B elements per vector
+  static_assert(AV * (P == 1 ? AE : 8) == A_SEG && BV * BE == B_SEG, "whole 16-byte segments");
+  uint4 va[P][AV], vo[P == 1 ? AV : 1], vb[P][BV];
+  auto ld16 = [](const void* p) { return *reinterpret_cast<const uint4*>(p); };
+  auto st16 = [](void* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; };
+#define DE_ROT_FETCH(K0)                                                                  \
+  do {                                                                                    \
+    const int64_t k0_ = (K0);                                                             \
+    if constexpr (P == 1) {                                                               \
+      _Pragma("unroll") for (int q = 0; q < AV; ++q) {                                   \
+        va[0][q] = ld16(arow + k0_ + q * AE);                                             \
+        vo[q] = ld16(orow + k0_ + q * AE); /* padding columns are zero on both sides */   \
+      }                                                                                   \
+    } else {                                                                              \
+      _Pragma("unroll") for (int g = 0; g < AV; ++g)                                     \
+        _Pragma("unroll") for (int p = 0; p < P; ++p)                                    \
+          va[p][g] = ld16(aprow + (k0_ / 8 + g) * P * 8 + p * 8);                         \
+    }                                                                                     \
+    _Pragma("unroll") for (int p = 0; p < P; ++p)                                        \
+      _Pragma("unroll") for (int q = 0; q < BV; ++q) vb[p][q] = ld16(brow[p] + k0_ + q * BE); \
+  } while (0)
+#define DE_ROT_STASH(BUF)                                                                 \
+  do {                                                                                    \
+    const int b_ = (BUF);                                                                 \
+    if constexpr (P == 1) {                                                               \
+      _Pragma("unroll") for (int q = 0; q < AV; ++q) {                                   \
+        if constexpr (sizeof(T) == 4) {                                                   \
+          const float4 x = __builtin_bit_cast(float4, va[0][q]);                         \
+          const float4 y = __builtin_bit_cast(float4, vo[q]);                            \
+          st16(&As[b_][0][a_r][a_k + q * AE],                                             \
+               __builtin_bit_cast(uint4, make_float4(x.x - y.x, x.y - y.y, x.z - y.z, x.w - y.w))); \
+        } else {                                                                          \
+          const double2 x = __builtin_bit_cast(double2, va[0][q]);                       \
+          const double2 y = __builtin_bit_cast(double2, vo[q]);                          \
+          st16(&As[b_][0][a_r][a_k + q * AE],                                             \
+               __builtin_bit_cast(uint4, make_double2(x.x - y.x, x.y - y.y)));           \
+        }                                                                                 \
+      }                                                                                   \
+    } else {                                                                              \
+      _Pragma("unroll") for (int p = 0; p < P; ++p)                                      \
+        _Pragma("unroll") for (int q = 0; q < AV; ++q) st16(&As[b_][p][a_r][a_k + q * 8], va[p][q]); \
+    }                                                                                     \
+    _Pragma("unroll") for (int p = 0; p < P; ++p)                                        \
+      _Pragma("unroll") for (int q = 0; q < BV; ++q) st16(&Bs[b_][p][b_r][b_k + q * BE], vb[p][q]); \
+  } while (0)
 
   using Acc = typename std::conditional<MODE == MM_FP64, f64x4, f32x4>::type;
   Acc acc[WM][WN];
@@ -167,12 +223,12 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
       for (int r = 0; r < 4; ++r) acc[m][n][r] = 0;
 
   const int nk = static_cast<int>((D + KT - 1) / KT);
-  fetch(0);
-  stash(0);
+  DE_ROT_FETCH(0);
+  DE_ROT_STASH(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = NBUF == 2 ? (kt & 1) : 0;
-    if (kt + 1 < nk) fetch(static_cast<int64_t>(kt + 1) * KT);
+    if (kt + 1 < nk) DE_ROT_FETCH(static_cast<int64_t>(kt + 1) * KT);
     if constexpr (P == 1) {
 #pragma unroll
       for (int s = 0; s < KT / 4; ++s) {
@@ -220,12 +276,15 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
     }
     if constexpr (NBUF == 1) {
       __syncthreads();  // every wave is done with the slice before it is replaced
-      if (kt + 1 < nk) stash(0);
+      if (kt + 1 < nk) DE_ROT_STASH(0);
     } else {
-      if (kt + 1 < nk) stash(buf ^ 1);
+      if (kt + 1 < nk) DE_ROT_STASH(buf ^ 1);
     }
     __syncthreads();
   }
+
+#undef DE_ROT_FETCH
+#undef DE_ROT_STASH
 
   // ---- epilogue: sum_k w_k z_ik^2 over this block's columns ----
   const T* w = static_cast<const T*>(Pr.w);
@@ -385,6 +444,13 @@ hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s) {
 
 static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, GenNo gh,
                        int64_t rows, hipStream_t s) {
+  if (h.mm == MM_BF16X3 || h.mm == MM_BF16X6) {
+    const unsigned sb = nb(rows * h.ldk / 8, 256);
+    if (h.mm == MM_BF16X3)
+      hipLaunchKernelGGL(k_rot_split<2>, dim3(sb), dim3(256), 0, s, runs, run, src, gh, rows);
+    else
+      hipLaunchKernelGGL(k_rot_split<3>, dim3(sb), dim3(256), 0, s, runs, run, src, gh, rows);
+  }
   const int bm = tile_m_of(h.mm), bn = tile_n_of(h.mm);
   const int64_t blocks = ((rows + bm - 1) / bm) * ((h.D + bn - 1) / bn);
   switch (h.mm) {
