@@ -91,22 +91,33 @@ template <int P>
 __global__ void __launch_bounds__(256) k_rot_split(const RunDev* __restrict__ runs, int32_t run,
                                                   int src, GenNo ghn, int64_t rows) {
   const RunDev& Pr = runs[run];
-  const int64_t ldk = Pr.ldk, D = Pr.D;
+  const int64_t ldk = Pr.ldk;  // equals the population pitch ld
   const int64_t e = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * 8;
   if (e >= rows * ldk) return;
   const int64_t i = e / ldk, k0 = e % ldk;  // ldk is a multiple of 32
-  const float* a = a_row<float>(Pr, src, gen_value(ghn), i);
-  const float* o = static_cast<const float*>(Pr.o);
-  __attribute__((aligned(16))) __bf16 h[8], m[8], l[8];
+  // padding columns are zero in every row source and in the shift
+  const float4* a = reinterpret_cast<const float4*>(a_row<float>(Pr, src, gen_value(ghn), i) + k0);
+  const float4* o = reinterpret_cast<const float4*>(static_cast<const float*>(Pr.o) + k0);
+  const float4 a0 = a[0], a1 = a[1], o0 = o[0], o1 = o[1];
+  const float d[8] = {a0.x - o0.x, a0.y - o0.y, a0.z - o0.z, a0.w - o0.w,
+                      a1.x - o1.x, a1.y - o1.y, a1.z - o1.z, a1.w - o1.w};
+  uint32_t h[4], m[4], l[4];  // pairs of bf16 pieces
 #pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    const int64_t k = k0 + v;
-    split3(k < D ? a[k] - o[k] : 0.0f, h[v], m[v], l[v]);
+  for (int v = 0; v < 4; ++v) {
+    __bf16 h0, m0, l0, h1, m1, l1;
+    split3(d[2 * v], h0, m0, l0);
+    split3(d[2 * v + 1], h1, m1, l1);
+    h[v] = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h0)) |
+           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h1)) << 16);
+    m[v] = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, m0)) |
+           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, m1)) << 16);
+    l[v] = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, l0)) |
+           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, l1)) << 16);
   }
-  __bf16* out = static_cast<__bf16*>(Pr.apc) + (i * (ldk / 8) + k0 / 8) * P * 8;
-  copy16<__bf16, 8>(out, h);
-  copy16<__bf16, 8>(out + 8, m);
-  if constexpr (P == 3) copy16<__bf16, 8>(out + 16, l);
+  uint4* out = reinterpret_cast<uint4*>(static_cast<__bf16*>(Pr.apc) + (i * (ldk / 8) + k0 / 8) * P * 8);
+  out[0] = make_uint4(h[0], h[1], h[2], h[3]);
+  out[1] = make_uint4(m[0], m[1], m[2], m[3]);
+  if constexpr (P == 3) out[2] = make_uint4(l[0], l[1], l[2], l[3]);
 }
 
 // The product for one 128x128 (FP64: 64x64) tile of Z.  The next K slice is
