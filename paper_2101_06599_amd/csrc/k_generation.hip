@@ -282,7 +282,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
 
   // Alg 2 lines 8-10 for this row: trial = parent with the masked elements
   // replaced by x_r0 + F (x_r1 - x_r2), evaluated on the fly.
-  // Phase 1 (64-lane rows of one run): every cached chunk's parent (and
+  // Phase 1 (64- and 128-lane rows of one run): every cached chunk's parent (and
   // shift) loads go out together; wide rows and batched launches, where
   // occupancy matters more, load each chunk as they reach it.
   constexpr bool kPrefetch = S::PREFETCH && !BATCH;

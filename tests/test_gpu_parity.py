@@ -521,12 +521,14 @@ def test_full_size_rotated_4096x2048(mm, dtype):
 
 # ---- captured graphs replay the same generations ------------------------------
 
-@pytest.mark.parametrize("kind", ["nec", "rotated", "batched"])
+@pytest.mark.parametrize("kind", ["nec", "nec_partial", "rotated", "batched"])
 def test_graph_replay_matches_direct_launches(kind):
     from paper_2101_06599_amd import synth
     rot = None
     if kind == "nec":
         cfgs = [rast(N=64, D=300, xo="nec", dtype="fp64")]
+    elif kind == "nec_partial":
+        cfgs = [rast(N=64, D=300, CR=0.7, xo="nec", dtype="fp32", wb="partial")]
     elif kind == "rotated":
         rot = rotation(96, 3)
         cfgs = [ell("fp32", "fp32", D=96, N=40, xo="bin")]
