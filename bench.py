@@ -291,7 +291,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the method has no cross-GPU path in this build)", file=sys.stderr)
+              "(there is no cross-GPU path)", file=sys.stderr)
         sys.exit(2)
 
     import torch
