@@ -409,6 +409,31 @@ def test_sin_squared_term_accuracy(fn, dtype):
     assert bad.size == 0, (bad[:5], Xr[bad[:5], 0], f[bad[:5]], fr[bad[:5]])
 
 
+@pytest.mark.parametrize("mm,dtype,tol", [("fp64", "fp64", 1e-12), ("fp32", "fp32", 1e-5),
+                                          ("bf16x6", "fp32", 1e-6), ("bf16x3", "fp32", 1e-4)])
+def test_rotated_closed_forms(mm, dtype, tol):
+    """Orthogonal M with a known effect, so f has a closed form without the
+    oracle: M = I gives sum_k w_k d_k^2 and a permutation matrix P gives
+    sum_k w_k d_{perm(k)}^2, with d = x - o."""
+    import torch
+    D = 200
+    w = oracle.ellipsoid_weights(D)
+    rng = np.random.default_rng(9)
+    perm = rng.permutation(D)
+    for permuted, M in ((False, np.eye(D)), (True, np.eye(D)[perm])):
+        cfg = ell(mm, dtype, D=D, N=40)
+        gpu = DE([cfg], M)
+        o = oracle_run(cfg, rot=M, lazy=True).shift()
+        dt = torch.float64 if dtype == "fp64" else torch.float32
+        Xd = torch.as_tensor(rng.uniform(-100, 100, (60, D)), dtype=dt, device="cuda:0")
+        Xr = Xd.cpu().numpy().astype(np.float64)
+        f = gpu.evaluate(0, Xd).cpu().numpy().astype(np.float64)
+        d = Xr - o
+        closed = (w * (d[:, perm] if permuted else d) ** 2).sum(1)
+        assert np.all(np.abs(f - closed) <= tol * closed), (mm, float(np.max(np.abs(f - closed) / closed)))
+        gpu.close()
+
+
 def test_evaluate_rotated():
     import torch
     D = 200
