@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-             "-Wall", "-o", tmp, os.path.join(_HERE, "oracle.c"), "-lm"])
+             "-fopenmp", "-Wall", "-o", tmp, os.path.join(_HERE, "oracle.c"), "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -101,6 +101,8 @@ def lib():
                                        C.c_int64]
         L.oracle_get_best.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_get_shift.argtypes = [C.c_void_p, f64p]
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = C.c_int
         L.oracle_individual.argtypes = [C.c_void_p, f64p, C.c_int64, C.c_int64, i64p, u8p, f64p,
                                         C.POINTER(C.c_double)]
         _lib = L
@@ -148,6 +150,12 @@ def indices_scheme(seed, run, base, N, g, i):
     r = np.zeros(3, np.int64)
     lib().oracle_indices_scheme(seed, run, BASE[base], N, g, i, r)
     return r
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads for a generation's per-individual loops (0: unchanged); returns
+    the count in effect.  Results do not depend on it."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def permute(seed, run, tag, g, N, k) -> int:

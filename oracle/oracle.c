@@ -7,7 +7,7 @@
  * synchronous (all trials of generation g are built from generation g-1's
  * population before any selection), which is what Alg 2 does.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared oracle.c -lm  (no fast-math:
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared oracle.c -lm  (no fast-math:
  * the trial arithmetic must round exactly as written).
  */
 #include "oracle.h"
@@ -15,6 +15,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4x32 S-box       */
@@ -426,6 +429,7 @@ oracle_state* oracle_create(const oracle_desc* d) {
   for (int64_t i = 0; i < N; ++i)
     for (int64_t j = 0; j < D; ++j)
       s->x[i * D + j] = init_value(d, OR_TAG_INIT, (uint32_t)i, j, d->lo, d->hi);
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) s->fit[i] = d->lazy ? NAN : eval_row(s, s->x + i * D);
   s->gen = 0;
   s->best_f = INFINITY;
@@ -502,6 +506,9 @@ static void one_generation(oracle_state* s) {
   const oracle_desc* d = &s->d;
   int64_t N = d->N, D = d->D;
   uint32_t g = (uint32_t)(s->gen + 1);
+  /* the N trials are independent (each reads x and writes its own row of
+   * the scratch arrays), so an OpenMP build gives the same bits */
+#pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < N; ++k) {
     int64_t i = row_of(d, g, k);
     build_trial(s, s->x, g, k, s->tr + 6 * i, s->mask + i * D, s->u + i * D, s->fu + i);
@@ -567,4 +574,14 @@ void oracle_get_best(const oracle_state* s, double* f, int64_t* idx, int64_t* ge
 
 void oracle_get_shift(const oracle_state* s, double* o) {
   memcpy(o, s->o, sizeof(double) * s->d.D);
+}
+
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }

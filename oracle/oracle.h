@@ -111,6 +111,10 @@ void oracle_set_state(oracle_state* s, const double* pop, const double* fit, int
                       double best_f, int64_t best_idx, int64_t best_gen);
 void oracle_get_best(const oracle_state* s, double* f, int64_t* idx, int64_t* gen, double* xbest);
 void oracle_get_shift(const oracle_state* s, double* o);
+/* Threads used for the per-individual loops of a generation (OpenMP build);
+ * n <= 0 leaves the count unchanged.  Returns the count now in effect (1 when
+ * built without OpenMP).  Results do not depend on it. */
+int oracle_set_threads(int n);
 /* Generation g's trial for the individual stored in row i, built from the
  * population `pop` (N x D, the population after generation g-1): idx6 = r0,
  * r1, r2 (rows read), jrand, L, 0; mask and trial D values; *ftrial =

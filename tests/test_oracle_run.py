@@ -168,3 +168,29 @@ def test_fp32_trials_are_float_values():
     t = r.generation(1, trace=True)
     tr = t["trial"]
     assert np.array_equal(tr.astype(np.float32).astype(np.float64), tr)
+
+
+@pytest.mark.parametrize("xo,fn,base,shuffle", [("nec", "rastrigin", "classic", False),
+                                                ("bin", "griewank", "perm", True),
+                                                ("exp", "rosenbrock", "offset", True)])
+def test_openmp_build_matches_one_thread(xo, fn, base, shuffle):
+    """The per-individual loops run in parallel: 1 and 4 threads give the
+    same bits (populations, fitness, decisions, best record)."""
+    kw = dict(N=37, D=23, F=0.6, CR=0.7, xo=xo, fn=fn, lo=-5.0, hi=5.0, olo=-1.0, ohi=1.0,
+              seed=4, base=base, shuffle=shuffle)
+    outs = []
+    before = oracle.set_threads(0)
+    try:
+        for n in (1, 4):
+            oracle.set_threads(n)
+            r = oracle.Run(**kw)
+            r.generation(20)
+            t = r.generation(1, trace=True)
+            outs.append((r.state(), r.best(), t))
+    finally:
+        oracle.set_threads(before)
+    (s1, b1, t1), (s4, b4, t4) = outs
+    assert np.array_equal(s1[0], s4[0]) and np.array_equal(s1[1], s4[1]) and s1[2] == s4[2]
+    assert b1[:3] == b4[:3] and np.array_equal(b1[3], b4[3])
+    for k in t1:
+        assert np.array_equal(t1[k], t4[k]), k
