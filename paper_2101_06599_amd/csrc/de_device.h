@@ -285,6 +285,40 @@ __device__ __forceinline__ float sinpi_sq(float z) {
   return sv * sv;
 }
 
+// 20 sin^2(pi z), the Rastrigin term's periodic part: the same series with
+// every coefficient multiplied by sqrt(20) (saves the final multiply).
+__device__ __forceinline__ double sinpi_sq20(double z) {
+  const double r = z - __builtin_rint(z);
+  const double t = r * r;
+  double p = 0x1.4b7532d364c22p-29;
+  p = __builtin_fma(p, t, -0x1.b8c93914521bcp-24);
+  p = __builtin_fma(p, t, 0x1.dd50645e071b8p-19);
+  p = __builtin_fma(p, t, -0x1.9b13c2e21891dp-14);
+  p = __builtin_fma(p, t, 0x1.115563fac6825p-9);
+  p = __builtin_fma(p, t, -0x1.0e056bbc9d3a6p-5);
+  p = __builtin_fma(p, t, 0x1.782f347fc49e3p-2);
+  p = __builtin_fma(p, t, -0x1.5709fe17202dep+1);
+  p = __builtin_fma(p, t, 0x1.6cf3241671f24p+3);
+  p = __builtin_fma(p, t, -0x1.71c57c2da483dp+4);
+  p = __builtin_fma(p, t, 0x1.c196908691da7p+3);
+  const double sv = r * p;
+  return sv * sv;
+}
+
+__device__ __forceinline__ float sinpi_sq20(float z) {
+  const float r = z - __builtin_rintf(z);
+  const float t = r * r;
+  float p = 0x1.115564p-9f;
+  p = __builtin_fmaf(p, t, -0x1.0e056cp-5f);
+  p = __builtin_fmaf(p, t, 0x1.782f34p-2f);
+  p = __builtin_fmaf(p, t, -0x1.5709fep+1f);
+  p = __builtin_fmaf(p, t, 0x1.6cf324p+3f);
+  p = __builtin_fmaf(p, t, -0x1.71c57cp+4f);
+  p = __builtin_fmaf(p, t, 0x1.c19690p+3f);
+  const float sv = r * p;
+  return sv * sv;
+}
+
 // Separable per-element term: sphere x^2, Rastrigin z^2 + 20 sin^2(pi z)
 // (= z^2 - 10 cos(2 pi z) + 10 without the cancellation near integers).
 template <typename T, int FN>
@@ -293,7 +327,7 @@ __device__ __forceinline__ T point_term(T x, T o) {
     return x * x;
   } else {
     const T z = x - o;
-    return Math<T>::fma_(z, z, T(20) * sinpi_sq(z));
+    return Math<T>::fma_(z, z, sinpi_sq20(z));
   }
 }
 
