@@ -24,7 +24,10 @@
  *    DE_E_HIP; errors of earlier asynchronous work surface at the next call
  *    that synchronises.  de_last_error() returns a message for the last
  *    failure on that handle.
- *  - A handle is not thread-safe; distinct handles are independent.
+ *  - A handle is not thread-safe; distinct handles are independent.  Work of
+ *    one handle enqueued on different streams must be ordered by the caller
+ *    (events or synchronisation): generations and evaluations share the
+ *    handle's workspace (populations, staging rows, partial sums).
  *  - Population layout in host buffers and in caller device buffers: dense
  *    row-major N x D of the run's dtype (individual i is row i).
  *
@@ -218,9 +221,10 @@ de_status de_trace(de_handle* h, int32_t run, int64_t* idx, uint8_t* mask, void*
 
 /* Kernel timing for measurement: while enabled, de_generation records HIP
  * events on the launch stream around the generation's main kernel: around
- * each launch when a generation takes several kernels (rotated function, or
- * the job-per-individual exponential crossover), else around the whole run
- * of back-to-back generation launches of the call.  de_profile_read syncs
+ * each launch when a generation takes several kernels (the rotated
+ * function's product, with its bf16 split pass in the split-bf16 modes, or
+ * the job-per-individual exponential crossover's trial kernel), else around
+ * the whole run of back-to-back generation launches of the call.  de_profile_read syncs
  * and returns the elapsed milliseconds recorded since enabling and the number
  * of main-kernel launches they cover. */
 de_status de_profile(de_handle* h, int32_t enable);
