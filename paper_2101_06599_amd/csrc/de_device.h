@@ -397,6 +397,21 @@ __device__ __forceinline__ T wave_stat2(T v) {
   }
 }
 
+// Pieces of a value for the split-bf16 products: hi = bf16(v), then the
+// rounding remainders (hi + mid + lo carries the 24 bits of an FP32 value).
+__device__ __forceinline__ void split3(float v, __bf16& a, __bf16& b, __bf16& c) {
+  a = static_cast<__bf16>(v);
+  const float r1 = v - static_cast<float>(a);
+  b = static_cast<__bf16>(r1);
+  const float r2 = r1 - static_cast<float>(b);
+  c = static_cast<__bf16>(r2);
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(__bf16 a, __bf16 b) {
+  return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, a)) |
+         (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, b)) << 16);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

@@ -15,6 +15,7 @@ enum : int { EXPI_LANE = 0, EXPI_JOB = 1, EXPI_SCAN = 2 };
 enum : uint32_t { TAG_INIT = 1, TAG_SHIFT = 2, TAG_IDX = 3, TAG_XO = 4, TAG_BIN = 5, TAG_EXP = 6,
                   TAG_OFFSET = 7, TAG_PERM = 8, TAG_SHUFFLE = 9 };
 enum : int { BASE_CLASSIC = 0, BASE_RANDOM = 1, BASE_OFFSET = 2, BASE_PERM = 3 };
+enum : int { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3 };  // rotated product modes
 
 // Best so far of one run, as of generation g.  Kernels of a generation get
 // the handle's generation number as an argument (the host knows it without
@@ -138,8 +139,9 @@ hipError_t launch_masks(const RunDev* runs, const RunDev& h, int run, uint32_t g
 // N rows (the trials of the coming generation when `trials`, else the
 // population) into fit_dst or, when select, straight into greedy selection.
 hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s);
+// split: false when the trial kernel has written the bf16 pieces already
 hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
-                              hipStream_t s);
+                              bool split, hipStream_t s);
 hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
                              hipStream_t s);
 hipError_t launch_rot_init_fit(const RunDev* runs, const RunDev& h, int run, hipStream_t s);

@@ -290,7 +290,8 @@ de_status generation_launches(de_handle* h, hipStream_t s, de::GenNo gnew) {
           HIPCHECK(h, de::launch_generation(L, de::FN_NONE, d.xo, d.dtype, false));
         }
         mark();
-        HIPCHECK(h, de::launch_rot_fitness(h->dev_runs, H, r, gnew, s));
+        // the fused trial kernel writes the bf16 pieces; the p-exp one does not
+        HIPCHECK(h, de::launch_rot_fitness(h->dev_runs, H, r, gnew, job, s));
         mark();
         HIPCHECK(h, de::launch_rot_select(h->dev_runs, H, r, gnew, s));
       } else if (job) {

@@ -30,6 +30,24 @@ __device__ __forceinline__ V4<T> load4(const DE_GLOBAL T* p) {
   return r;
 }
 
+// Split-bf16 rotated runs: the np bf16 pieces of one chunk of (trial - o),
+// written where the product reads them (groups of 8 elements; piece p of
+// chunk c at row + ((c / 2) * np + p) * 8 + (c % 2) * 4), so no separate
+// split pass over the trial rows is needed.
+template <typename T>
+__device__ __forceinline__ void store_pieces(DE_GLOBAL __bf16* row, int np, uint32_t c,
+                                             const T (&u)[4], const V4<T>& o) {
+  if constexpr (sizeof(T) == 4) {
+    __bf16 h[4], m[4], l[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) split3(u[e] - o.v[e], h[e], m[e], l[e]);
+    DE_GLOBAL __bf16* q = row + (c >> 1) * np * 8 + (c & 1u) * 4;
+    *(DE_GLOBAL uint2*)q = make_uint2(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]));
+    *(DE_GLOBAL uint2*)(q + 8) = make_uint2(pack_bf16(m[0], m[1]), pack_bf16(m[2], m[3]));
+    if (np == 3) *(DE_GLOBAL uint2*)(q + 16) = make_uint2(pack_bf16(l[0], l[1]), pack_bf16(l[2], l[3]));
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void store4(DE_GLOBAL T* p, const T (&u)[4]) {
   if constexpr (sizeof(T) == 4) {
@@ -287,7 +305,12 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   // occupancy matters more, load each chunk as they reach it.
   constexpr bool kPrefetch = S::PREFETCH && !BATCH;
   constexpr bool kShift = FN == FN_RASTRIGIN || FN == FN_ROSENBROCK || FN == FN_ANY;
-  const bool shifted = kShift && (FN != FN_ANY || fn != FN_SPHERE);
+  // Rotated split-bf16 runs (FP32 only) also write the pieces of trial - o.
+  const bool pieces = FN == FN_NONE && sizeof(T) == 4 && P.apc != nullptr;
+  const int np = P.mm == MM_BF16X6 ? 3 : 2;
+  DE_GLOBAL __bf16* prow = pieces ? gmut<__bf16>(P.apc) + static_cast<int64_t>(si) * np * P.ldk
+                                  : nullptr;
+  const bool shifted = (kShift && (FN != FN_ANY || fn != FN_SPHERE)) || pieces;
   V4<T> xs[MAXIT], os[MAXIT];
   if constexpr (kPrefetch) {
     // Unconditional (lanes past the row reload its last chunk), so that the
@@ -413,23 +436,29 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
 #pragma unroll
       for (int k = 0; k < MAXIT; ++k) {
         const uint32_t c = k * TPR + t;
-        if (c < nchunk) store4(R.dst + 4 * c, u[k]);
+        if (c < nchunk) {
+          store4(R.dst + 4 * c, u[k]);
+          if (pieces) store_pieces(prow, np, c, u[k], os[k]);
+        }
       }
       for (uint32_t c = MAXIT * TPR + t; c < nchunk; c += TPR) {
         T v[4];
         build_chunk(P, R, c, v);
         store4(R.dst + 4 * c, v);
+        if (pieces) store_pieces(prow, np, c, v, load4(R.o + 4 * c));
       }
     } else {
 #pragma unroll
       for (int k = 0; k < MAXIT; ++k) {
         const uint32_t c = k * TPR + t;
         if (c < nchunk && (mb[k] != 0 || run_touches(pj, pl, c, R.D))) store4(R.dst + 4 * c, u[k]);
+        if (pieces && c < nchunk) store_pieces(prow, np, c, u[k], os[k]);
       }
       for (uint32_t c = MAXIT * TPR + t; c < nchunk; c += TPR) {
         T v[4];
         const uint32_t m = build_chunk(P, R, c, v);
         if (m != 0 || run_touches(pj, pl, c, R.D)) store4(R.dst + 4 * c, v);
+        if (pieces) store_pieces(prow, np, c, v, load4(R.o + 4 * c));
       }
     }
     if (t == 0 && pw != 0)

@@ -30,7 +30,6 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
-enum : int { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3 };
 
 template <int MODE> struct MM;
 template <> struct MM<MM_FP64> {
@@ -47,15 +46,6 @@ template <> struct MM<MM_BF16X6> {
 };
 
 int rot_tile_n() { return 128; }  // BN of the FP32/bf16 modes; FP64 uses 64 (2 partials per 128)
-
-// Pieces of a value: hi = bf16(v), then the rounding remainders.
-__device__ __forceinline__ void split3(float v, __bf16& a, __bf16& b, __bf16& c) {
-  a = static_cast<__bf16>(v);
-  const float r1 = v - static_cast<float>(a);
-  b = static_cast<__bf16>(r1);
-  const float r2 = r1 - static_cast<float>(b);
-  c = static_cast<__bf16>(r2);
-}
 
 // Row source for the A operand.
 //   src 0: trials of the coming generation (non-current buffer of each row)
@@ -107,12 +97,9 @@ __global__ void __launch_bounds__(256) k_rot_split(const RunDev* __restrict__ ru
     __bf16 h0, m0, l0, h1, m1, l1;
     split3(d[2 * v], h0, m0, l0);
     split3(d[2 * v + 1], h1, m1, l1);
-    h[v] = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h0)) |
-           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h1)) << 16);
-    m[v] = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, m0)) |
-           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, m1)) << 16);
-    l[v] = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, l0)) |
-           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, l1)) << 16);
+    h[v] = pack_bf16(h0, h1);
+    m[v] = pack_bf16(m0, m1);
+    l[v] = pack_bf16(l0, l1);
   }
   uint4* out = reinterpret_cast<uint4*>(static_cast<__bf16*>(Pr.apc) + (i * (ldk / 8) + k0 / 8) * P * 8);
   out[0] = make_uint4(h[0], h[1], h[2], h[3]);
@@ -453,9 +440,11 @@ hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s) {
   return hipGetLastError();
 }
 
+// split: write the bf16 pieces of the row source first (split-bf16 modes);
+// the trial kernel of a generation writes them itself.
 static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, GenNo gh,
-                       int64_t rows, hipStream_t s) {
-  if (h.mm == MM_BF16X3 || h.mm == MM_BF16X6) {
+                       int64_t rows, hipStream_t s, bool split = true) {
+  if (split && (h.mm == MM_BF16X3 || h.mm == MM_BF16X6)) {
     const unsigned sb = nb(rows * h.ldk / 8, 256);
     if (h.mm == MM_BF16X3)
       hipLaunchKernelGGL(k_rot_split<2>, dim3(sb), dim3(256), 0, s, runs, run, src, gh, rows);
@@ -475,8 +464,8 @@ static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, Ge
 }
 
 hipError_t launch_rot_fitness(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
-                              hipStream_t s) {
-  return gemm(runs, h, run, 0, gnew, h.N, s);
+                              bool split, hipStream_t s) {
+  return gemm(runs, h, run, 0, gnew, h.N, s, split);
 }
 
 hipError_t launch_rot_select(const RunDev* runs, const RunDev& h, int run, GenNo gnew,

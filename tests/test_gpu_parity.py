@@ -451,6 +451,28 @@ def test_evaluate_rotated():
         assert np.all(np.abs(f - fr) <= tol_of(cfg) * fr), mm
 
 
+@pytest.mark.parametrize("mm", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("wb,tpr,D", [("whole", 0, 160), ("partial", 0, 161), ("partial", 64, 1102),
+                                      ("whole", 64, 1102)])
+def test_rotated_trial_pieces_match_split(mm, wb, tpr, D):
+    """In the split-bf16 modes the trial kernel writes the bf16 pieces of
+    (trial - o) that the product reads, in place of a split pass over the trial
+    rows; de_evaluate still splits its rows.  Every stored fitness (winners'
+    trials and kept parents) must therefore equal de_evaluate of the stored
+    rows bit for bit.  Covers ragged D (odd last chunk), rows longer than the
+    register cache of a 64-lane row (tpr 64, D 1102) and both write-back modes."""
+    import torch
+    rot = rotation(D, 5)
+    cfg = ell(mm, "fp32", D=D, N=70, CR=0.6, wb=wb, tpr=tpr)
+    gpu = DE([cfg], rot)
+    for _ in range(4):
+        gpu.generation(1)
+        pop, fit, _ = gpu.state(0)
+        f = gpu.evaluate(0, torch.as_tensor(pop, device="cuda:0")).cpu().numpy()
+        assert np.array_equal(f, fit), (mm, wb, tpr, D, np.nonzero(f != fit)[0][:5])
+    gpu.close()
+
+
 def test_best_is_fp64_recompute_of_best_row():
     cfg = rast(dtype="fp32", N=40, D=200)
     gpu = DE([cfg])
