@@ -222,8 +222,9 @@ de_status de_trace(de_handle* h, int32_t run, int64_t* idx, uint8_t* mask, void*
 /* Kernel timing for measurement: while enabled, de_generation records HIP
  * events on the launch stream around the generation's main kernel: around
  * each launch when a generation takes several kernels (the rotated
- * function's product, with its bf16 split pass in the split-bf16 modes, or
- * the job-per-individual exponential crossover's trial kernel), else around
+ * function's product, with its bf16 split pass when the job-per-individual
+ * exponential crossover builds the trials, or that crossover's trial kernel),
+ * else around
  * the whole run of back-to-back generation launches of the call.  de_profile_read syncs
  * and returns the elapsed milliseconds recorded since enabling and the number
  * of main-kernel launches they cover. */
