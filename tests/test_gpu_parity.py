@@ -332,9 +332,10 @@ def test_rotated_ellipsoid(mm, dtype, xo):
     run_parity(ell(mm, dtype, xo=xo), 3, rot=rot)
 
 
-def test_rotated_ellipsoid_exp_job():
+@pytest.mark.parametrize("mm", ["fp32", "bf16x6"])
+def test_rotated_ellipsoid_exp_job(mm):
     rot = rotation(96, 1)
-    run_parity(ell("fp32", "fp32", D=96, N=70, xo="exp", exp_impl="job"), 2, rot=rot)
+    run_parity(ell(mm, "fp32", D=96, N=70, xo="exp", exp_impl="job"), 2, rot=rot)
 
 
 # ---- several runs in one launch --------------------------------------------
@@ -452,24 +453,29 @@ def test_evaluate_rotated():
 
 
 @pytest.mark.parametrize("mm", ["bf16x3", "bf16x6"])
-@pytest.mark.parametrize("wb,tpr,D", [("whole", 0, 160), ("partial", 0, 161), ("partial", 64, 1102),
-                                      ("whole", 64, 1102)])
-def test_rotated_trial_pieces_match_split(mm, wb, tpr, D):
+@pytest.mark.parametrize("extra", [dict(wb="whole", D=160), dict(wb="partial", D=161),
+                                   dict(wb="partial", tpr=64, D=1102),
+                                   dict(wb="whole", tpr=64, D=1102),
+                                   dict(D=161, base="perm", shuffle=True),
+                                   dict(D=161, xo="exp", exp_impl="job")])
+def test_rotated_trial_pieces_match_split(mm, extra):
     """In the split-bf16 modes the trial kernel writes the bf16 pieces of
     (trial - o) that the product reads, in place of a split pass over the trial
     rows; de_evaluate still splits its rows.  Every stored fitness (winners'
     trials and kept parents) must therefore equal de_evaluate of the stored
     rows bit for bit.  Covers ragged D (odd last chunk), rows longer than the
-    register cache of a 64-lane row (tpr 64, D 1102) and both write-back modes."""
+    register cache of a 64-lane row (tpr 64, D 1102), both write-back modes,
+    the shuffle, and the exp-job trials (which keep the split pass)."""
     import torch
-    rot = rotation(D, 5)
-    cfg = ell(mm, "fp32", D=D, N=70, CR=0.6, wb=wb, tpr=tpr)
+    cfg = ell(mm, "fp32", N=70, CR=0.6)
+    cfg.update(extra)
+    rot = rotation(cfg["D"], 5)
     gpu = DE([cfg], rot)
     for _ in range(4):
         gpu.generation(1)
         pop, fit, _ = gpu.state(0)
         f = gpu.evaluate(0, torch.as_tensor(pop, device="cuda:0")).cpu().numpy()
-        assert np.array_equal(f, fit), (mm, wb, tpr, D, np.nonzero(f != fit)[0][:5])
+        assert np.array_equal(f, fit), (mm, extra, np.nonzero(f != fit)[0][:5])
     gpu.close()
 
 
