@@ -128,10 +128,9 @@ typedef struct {
   int32_t exp_impl; /* de_exp_impl, DE_XO_EXP only */
   int32_t tpr;      /* lanes per individual in the generation kernel: 0 = chosen
                        from D, N and dtype; 64, 128, 256, 512 or 1024 forces
-                       it (batched: 0
-                       or 64).
-                       Indices, masks and trial rows do not depend on it;
-                       fitness sums only change their rounding order. */
+                       it (batched: 0 or 64).  Indices, masks and trial rows
+                       do not depend on it; fitness sums only change their
+                       rounding order. */
   int32_t base;     /* de_base */
   int32_t shuffle;  /* 1: shuffle the individuals at the start of every
                        generation (Alg 2 line 5), 0: do not.  Applied as a
@@ -224,10 +223,9 @@ de_status de_trace(de_handle* h, int32_t run, int64_t* idx, uint8_t* mask, void*
  * each launch when a generation takes several kernels (the rotated
  * function's product, with its bf16 split pass when the job-per-individual
  * exponential crossover builds the trials, or that crossover's trial kernel),
- * else around
- * the whole run of back-to-back generation launches of the call.  de_profile_read syncs
- * and returns the elapsed milliseconds recorded since enabling and the number
- * of main-kernel launches they cover. */
+ * else around the whole run of back-to-back generation launches of the call.
+ * de_profile_read syncs and returns the elapsed milliseconds recorded since
+ * enabling and the number of main-kernel launches they cover. */
 de_status de_profile(de_handle* h, int32_t enable);
 de_status de_profile_read(de_handle* h, double* main_ms, int64_t* main_launches);
 
