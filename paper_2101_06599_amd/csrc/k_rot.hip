@@ -36,7 +36,7 @@ template <> struct MM<MM_FP64> {
   using T = double; using L = double; static constexpr int P = 1, KT = 16, BM = 64, BN = 64, PAD = 2;
 };
 template <> struct MM<MM_FP32> {
-  using T = float; using L = float; static constexpr int P = 1, KT = 16, BM = 128, BN = 128, PAD = 4;
+  using T = float; using L = float; static constexpr int P = 1, KT = 32, BM = 128, BN = 128, PAD = 4;
 };
 template <> struct MM<MM_BF16X3> {
   using T = float; using L = __bf16; static constexpr int P = 2, KT = 32, BM = 128, BN = 128, PAD = 8;
