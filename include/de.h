@@ -141,7 +141,8 @@ typedef struct {
   int32_t wb;       /* winners' write-back into the row's other buffer:
                        0 = chosen from the population size (whole rows while
                        one buffer of the handle fits in 48 MiB, else only the
-                       changed chunks), 1 = whole rows, 2 = only the chunks in
+                       changed chunks; always the latter for ELLIPSOID_ROT),
+                       1 = whole rows, 2 = only the chunks in
                        which the two buffers differ (exp and NEC; binomial
                        rows are always written whole).  Results do not depend
                        on it. */

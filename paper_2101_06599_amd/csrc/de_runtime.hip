@@ -451,8 +451,12 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
   size_t pop_bytes = 0;
   for (int r = 0; r < n_runs; ++r)
     pop_bytes += static_cast<size_t>(esz(runs[r].dtype)) * runs[r].N * L.r[r].ld;
+  // Rotated runs always: their generation is dominated by the product, and
+  // the trial kernel's smaller stores measured faster at every size tried.
   for (int r = 0; r < n_runs; ++r)
-    h->host[r].partial_wb = runs[r].wb == 2 || (runs[r].wb == 0 && pop_bytes > (size_t(48) << 20));
+    h->host[r].partial_wb = runs[r].wb == 2 ||
+                            (runs[r].wb == 0 && (pop_bytes > (size_t(48) << 20) ||
+                                                 runs[r].fn == DE_FN_ELLIPSOID_ROT));
   h->single_kernel = true;
   for (int r = 0; r < n_runs; ++r)
     if (runs[r].fn == DE_FN_ELLIPSOID_ROT || (runs[r].xo == DE_XO_EXP && runs[r].exp_impl == DE_EXP_JOB))
