@@ -84,6 +84,10 @@ def lib():
         L.oracle_nec_length_log.restype = C.c_int64
         L.oracle_alg9_mask.argtypes = [C.c_int64, C.c_int64, C.c_int64, u8p]
         L.oracle_alg10_mask.argtypes = [C.c_int64, C.c_int64, C.c_int64, u8p]
+        L.oracle_lengths.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_int64, C.c_double,
+                                     C.c_int64, i64p]
+        L.oracle_ackley_printed.argtypes = [C.c_int64, f64p]
+        L.oracle_ackley_printed.restype = C.c_double
         fitargs = [C.c_int, C.c_int64, f64p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_fitness.argtypes = fitargs
         L.oracle_fitness.restype = C.c_double
@@ -182,6 +186,20 @@ def nec_length_log(U, CR, D) -> int:
     return lib().oracle_nec_length_log(U, CR, D)
 
 
+def lengths(kind, D, CR, n, seed=11, run=0):
+    """Run lengths of n individuals (generation 1 + k // 4096, position
+    k % 4096): kind "exp" (Alg 8) or "nec" (Eq 9)."""
+    out = np.zeros(int(n), np.int64)
+    lib().oracle_lengths(0 if kind == "exp" else 1, seed, run, D, CR, int(n), out)
+    return out
+
+
+def ackley_printed(x) -> float:
+    """Ackley in the printed order of Sec. 4 (cross-check of fitness())."""
+    x = np.ascontiguousarray(x, np.float64)
+    return lib().oracle_ackley_printed(x.shape[-1], x)
+
+
 def alg9_mask(D, j, L):
     m = np.zeros(D, np.uint8)
     lib().oracle_alg9_mask(D, j, L, m)
@@ -227,7 +245,8 @@ def fitness(fn, x, o=None, rot=None, w=None):
 
 
 def fitness_phi(fn, x, o=None, rot=None, w=None):
-    """The tolerance scale: f evaluated on absolute sub-terms."""
+    """The tolerance scale: the absolute values of the terms whose rounding
+    the evaluation carries (f itself for sums of non-negative terms)."""
     return _fit_call(lib().oracle_fitness_phi, fn, x, o, rot, w)
 
 

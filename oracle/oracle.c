@@ -234,6 +234,20 @@ void oracle_alg10_mask(int64_t D, int64_t j, int64_t L, uint8_t* mask) {
   }
 }
 
+void oracle_lengths(int kind, uint64_t seed, uint32_t run, int64_t D, double CR, int64_t n,
+                    int64_t* out) {
+  for (int64_t k = 0; k < n; ++k) {
+    uint32_t g = (uint32_t)(1 + k / 4096);
+    int64_t i = k % 4096;
+    if (kind == 0) {
+      out[k] = oracle_exp_length(seed, run, D, CR, g, i);
+    } else {
+      uint32_t w = oracle_word(seed, run, OR_TAG_XO, g, (uint32_t)i, 0, 1);
+      out[k] = oracle_nec_length(oracle_uniform(w), CR, D);
+    }
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Fitness (Sec. 4 and the shifted/rotated forms used by the experiments).   */
 /* Sums in long double; NaN maps to +inf so that it never wins selection.    */
@@ -248,6 +262,41 @@ void oracle_ellipsoid_weights(int64_t D, double* w) {
 static double finite_or_inf(long double v) {
   double d = (double)v;
   return isnan(d) ? INFINITY : d;
+}
+
+/* Ackley (Sec. 4): -20 exp(-0.02 sqrt(mean x^2)) - exp(mean cos 2 pi x) + 20 + e.
+ * Written as the sum of two non-negative terms: with a = -0.02 sqrt(mean x^2)
+ * and cos(2 pi x) = 1 - 2 sin^2(pi x), exp(mean cos 2 pi x) = e exp(b) with
+ * b = -2 mean sin^2(pi x), so
+ *   f = 20 (1 - e^a) + e (1 - e^b) = -20 expm1(a) - e expm1(b).
+ * The printed order subtracts numbers close to 20 + e and keeps only their
+ * absolute accuracy near x = 0; this order keeps f's relative accuracy.  The
+ * sine is taken of pi r with r = x - nearest integer (exact in FP64), so its
+ * argument carries no rounding.  oracle_ackley_printed() evaluates the
+ * printed order for a cross-check. */
+static const long double E_L = 2.718281828459045235360287471352662498L;
+
+static void ackley_terms(int64_t D, const double* x, long double* t1, long double* t2) {
+  long double sq = 0.0L, s2 = 0.0L;
+  for (int64_t j = 0; j < D; ++j) {
+    sq += (long double)x[j] * (long double)x[j];
+    double r = x[j] - nearbyint(x[j]);
+    long double sn = sinl(PI_L * (long double)r);
+    s2 += sn * sn;
+  }
+  *t1 = -20.0L * expm1l(-0.02L * sqrtl(sq / (long double)D));
+  *t2 = -E_L * expm1l(-2.0L * s2 / (long double)D);
+}
+
+double oracle_ackley_printed(int64_t D, const double* x) {
+  long double sq = 0.0L, cs = 0.0L;
+  for (int64_t j = 0; j < D; ++j) {
+    sq += (long double)x[j] * (long double)x[j];
+    cs += cosl(2.0L * PI_L * (long double)x[j]);
+  }
+  long double s = -20.0L * expl(-0.02L * sqrtl(sq / (long double)D)) - expl(cs / (long double)D) +
+                  20.0L + E_L;
+  return finite_or_inf(s);
 }
 
 double oracle_fitness(int fn, int64_t D, const double* x, const double* o, const double* rot,
@@ -276,14 +325,9 @@ double oracle_fitness(int fn, int64_t D, const double* x, const double* o, const
       }
       break;
     case OR_FN_ACKLEY: {
-      /* Sec. 4, as printed: -20 exp(-0.02 sqrt(mean x^2)) - exp(mean cos 2 pi x) + 20 + e */
-      long double sq = 0.0L, cs = 0.0L;
-      for (int64_t j = 0; j < D; ++j) {
-        sq += (long double)x[j] * (long double)x[j];
-        cs += cosl(2.0L * PI_L * (long double)x[j]);
-      }
-      s = -20.0L * expl(-0.02L * sqrtl(sq / (long double)D)) - expl(cs / (long double)D) + 20.0L +
-          expl(1.0L);
+      long double t1, t2;
+      ackley_terms(D, x, &t1, &t2);
+      s = t1 + t2;
       break;
     }
     case OR_FN_GRIEWANK: {
@@ -313,19 +357,20 @@ double oracle_fitness(int fn, int64_t D, const double* x, const double* o, const
 
 double oracle_fitness_phi(int fn, int64_t D, const double* x, const double* o, const double* rot,
                           const double* w) {
-  if (fn == OR_FN_ACKLEY || fn == OR_FN_GRIEWANK) {
-    /* the final combination cancels near the optimum: scale by its parts */
-    long double sq = 0.0L, cs = 0.0L, pr = 1.0L;
+  if (fn == OR_FN_ACKLEY) {
+    /* the two terms of the cancellation-free form, each taken positive */
+    long double t1, t2;
+    ackley_terms(D, x, &t1, &t2);
+    return finite_or_inf(fabsl(t1) + fabsl(t2));
+  }
+  if (fn == OR_FN_GRIEWANK) {
+    /* 1 - prod cos cancels near the optimum: scale by the parts */
+    long double sq = 0.0L, pr = 1.0L;
     for (int64_t j = 0; j < D; ++j) {
       sq += (long double)x[j] * (long double)x[j];
-      if (fn == OR_FN_ACKLEY) cs += cosl(2.0L * PI_L * (long double)x[j]);
-      else pr *= cosl((long double)x[j] / sqrtl((long double)(j + 1)));
+      pr *= cosl((long double)x[j] / sqrtl((long double)(j + 1)));
     }
-    long double v = fn == OR_FN_ACKLEY
-                        ? 20.0L * expl(-0.02L * sqrtl(sq / (long double)D)) +
-                              expl(cs / (long double)D) + 20.0L + expl(1.0L)
-                        : sq / 4000.0L + fabsl(pr) + 1.0L;
-    return finite_or_inf(v);
+    return finite_or_inf(sq / 4000.0L + fabsl(pr) + 1.0L);
   }
   if (fn != OR_FN_ROSENBROCK) return oracle_fitness(fn, D, x, o, rot, w);
   long double s = 0.0L;

@@ -70,16 +70,28 @@ int64_t oracle_nec_length_log(double U, double CR, int64_t D);
 void oracle_alg9_mask(int64_t D, int64_t j, int64_t L, uint8_t* mask);
 /* Alg 10 with the comparison fixed (see oracle.c): elementwise run mask */
 void oracle_alg10_mask(int64_t D, int64_t j, int64_t L, uint8_t* mask);
+/* Run lengths of n individuals for the statistical pins: individual k is
+ * (generation 1 + k / 4096, position k % 4096) of the run.  kind 0: Alg 8
+ * (oracle_exp_length), kind 1: NEC (oracle_nec_length of XO word 1). */
+void oracle_lengths(int kind, uint64_t seed, uint32_t run, int64_t D, double CR, int64_t n,
+                    int64_t* out);
 
 /* ---- fitness ------------------------------------------------------------ */
 /* f(x); o may be NULL for the sphere; rot (D x D row-major) and w only for the
  * rotated ellipsoid.  Returns +inf for NaN. */
 double oracle_fitness(int fn, int64_t D, const double* x, const double* o, const double* rot,
                       const double* w);
-/* the same expression on absolute sub-terms (tolerance scale) */
+/* Tolerance scale: the sum of the absolute values of the terms whose rounding
+ * the evaluation carries.  Rosenbrock: each pair's parts |z_{j+1}| + z_j^2
+ * and |z_j| + 1; Griewank: sum x^2 / 4000 + |prod cos| + 1 (the final
+ * 1 - prod cancels); Ackley: the two terms of its cancellation-free form,
+ * which are both >= 0, so the scale is f itself; the sphere, Rastrigin and
+ * the ellipsoid are sums of non-negative terms: f. */
 double oracle_fitness_phi(int fn, int64_t D, const double* x, const double* o, const double* rot,
                           const double* w);
 void oracle_ellipsoid_weights(int64_t D, double* w);
+/* Ackley in the order Sec. 4 prints it (cross-check only) */
+double oracle_ackley_printed(int64_t D, const double* x);
 
 /* ---- a whole run --------------------------------------------------------- */
 typedef struct {
@@ -93,7 +105,7 @@ typedef struct {
   const double* rot;    /* D x D row-major, rotated ellipsoid only */
   int32_t lazy;         /* 1: skip the initial evaluation (per-individual use only) */
   int32_t base;         /* OR_BASE_* */
-  int32_t shuffle;      /* 1: shuffle the individuals every generation (Alg 2 line 5) */
+  int32_t shuffle;      /* 1: shuffle the individuals every generation (Alg 2) */
   int32_t pad;
 } oracle_desc;
 

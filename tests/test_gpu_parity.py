@@ -200,6 +200,33 @@ def test_two_statistic_evaluate_special_points(name, dtype):
     assert f[0] == 0.0 or abs(f[0]) <= 1e-15
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_ackley_near_optimum_relative_bar(dtype):
+    """Near x = 0 the tolerance scale of Ackley is f itself (both terms of its
+    cancellation-free form are >= 0), so the bar is tol * f: 1e-12 relative
+    in FP64, 1e-5 in FP32.  de_evaluate on rows at shrinking scales, then 30
+    generations of a run started in [-1e-4, 1e-4]^D."""
+    import torch
+    D = 1000
+    tol = 1e-12 if dtype == "fp64" else 1e-5
+    cfg = table2("ackley", D=D, N=64, dtype=dtype, lo=-1e-4, hi=1e-4)
+    gpu = DE([cfg])
+    rng = np.random.default_rng(21)
+    rows = [rng.uniform(-s, s, D) for s in (1e-1, 1e-3, 1e-5, 1e-7) for _ in range(4)]
+    dt = torch.float64 if dtype == "fp64" else torch.float32
+    Xd = torch.as_tensor(np.array(rows), dtype=dt, device="cuda:0")
+    Xr = Xd.cpu().numpy().astype(np.float64)
+    f = gpu.evaluate(0, Xd).cpu().numpy().astype(np.float64)
+    fr = oracle.fitness("ackley", Xr)
+    assert np.all(oracle.fitness_phi("ackley", Xr) == fr)
+    rel = np.abs(f - fr) / fr
+    assert np.all(rel <= tol), f"max relative error {rel.max():.3e}"
+    gpu.close()
+    _, ref, _ = run_parity(cfg, 30)
+    _, fit, _ = ref.state()
+    assert fit.max() < 1e-3  # the run stayed near the optimum
+
+
 @pytest.mark.parametrize("name", ["ackley", "griewank"])
 def test_two_statistic_best_and_many_generations(name):
     """200 generations at Table 2's F and Cr (smaller N, D): selection and the
@@ -406,6 +433,11 @@ def test_sin_squared_term_accuracy(fn, dtype):
     eps = 2.0 ** -52 if dtype == "fp64" else 2.0 ** -23
     zz = np.abs(Xr[:, 0] - (o[0] if fn == "rastrigin" else 0.0))
     bound = eps * (8 * phi + 80 * np.pi * zz * np.maximum(zz, 1.0))
+    if fn == "ackley":
+        # sum x^2 is formed in the working precision: below the smallest
+        # normal square it underflows, which moves -20 expm1(-0.02 sqrt(s1/D))
+        # by at most 0.4 sqrt(smallest normal) (x = 1e-300 is such a point)
+        bound = bound + 0.4 * np.sqrt(np.finfo(np.float64 if dtype == "fp64" else np.float32).tiny)
     bad = np.nonzero(np.abs(f - fr) > bound)[0]
     assert bad.size == 0, (bad[:5], Xr[bad[:5], 0], f[bad[:5]], fr[bad[:5]])
 

@@ -60,23 +60,37 @@ def merged_chisquare(obs, exp, min_exp=5.0):
 
 
 def sample_exp_lengths(D, CR, n, seed=11):
-    return np.array([oracle.exp_length(seed, 0, D, CR, 1 + k // 4096, k % 4096)
-                     for k in range(n)])
+    """Alg 8 run lengths of n individuals, sampled by the oracle's C loop."""
+    return oracle.lengths("exp", D, CR, n, seed)
 
 
 def sample_nec_lengths(D, CR, n, seed=11):
-    out = np.empty(n, np.int64)
-    for k in range(n):
-        w = oracle.word(seed, 0, "xo", 1 + k // 4096, k % 4096, 0, 1)
-        out[k] = oracle.nec_length(oracle.uniform(w), CR, D)
-    return out
+    """NEC (Eq 9) run lengths of n individuals, sampled by the oracle's C loop."""
+    return oracle.lengths("nec", D, CR, n, seed)
+
+
+def test_batch_sampler_is_the_per_individual_draw():
+    # the C loop addresses individual k as (generation 1 + k // 4096, position
+    # k % 4096) and calls the same per-individual functions
+    n = 5000
+    a = sample_exp_lengths(37, 0.8, n, seed=5)
+    b = sample_nec_lengths(37, 0.8, n, seed=5)
+    for k in range(0, n, 7):
+        g, i = 1 + k // 4096, k % 4096
+        assert a[k] == oracle.exp_length(5, 0, 37, 0.8, g, i)
+        w = oracle.word(5, 0, "xo", g, i, 0, 1)
+        assert b[k] == oracle.nec_length(oracle.uniform(w), 0.8, 37)
+
+
+# 10^6 draws per case, as in the L-frequency comparison of Sec. 3.2
+N_DRAWS = 1_000_000
 
 
 @pytest.mark.parametrize("D,CR", [(4, 0.5), (10, 0.2), (10, 0.5), (10, 0.9), (10, 0.95),
                                   (1000, 0.9), (1000, 0.95)])
 @pytest.mark.parametrize("kind", ["exp", "nec"])
 def test_length_law_geometric_truncated(kind, D, CR):
-    n = 60000
+    n = N_DRAWS
     L = sample_exp_lengths(D, CR, n) if kind == "exp" else sample_nec_lengths(D, CR, n)
     assert L.min() >= 1 and L.max() <= D
     obs = np.bincount(L, minlength=D + 1)[1:]
@@ -86,6 +100,18 @@ def test_length_law_geometric_truncated(kind, D, CR):
     mean = (1 - CR**D) / (1 - CR)
     sd = np.sqrt(((np.arange(1, D + 1) - mean) ** 2 * exp / n).sum())
     assert abs(L.mean() - mean) < 5 * sd / np.sqrt(n)
+    # the tail P(L >= k) = Cr^(k-1) itself at a few k, within 5 binomial sd
+    for k in (2, 3, 5, 10):
+        if k <= D:
+            p = CR ** (k - 1)
+            assert abs(np.mean(L >= k) - p) <= 5 * np.sqrt(p * (1 - p) / n) + 1e-12
+
+
+def test_length_law_detects_a_shifted_law():
+    # power check: the 10^6-draw test rejects a law whose ratio is off by 1 %
+    n = N_DRAWS
+    L = sample_nec_lengths(10, 0.9, n)
+    assert merged_chisquare(np.bincount(L, minlength=11)[1:], geometric_expected(0.9 * 1.01, 10, n)) < 1e-3
 
 
 @pytest.mark.parametrize("D", [1, 4, 10, 1000])
@@ -97,8 +123,8 @@ def test_length_special_cases(kind, D):
 
 
 def test_exp_and_nec_lengths_homogeneous_d10():
-    # the claim of the L-frequency comparison for D = 10 in Sec. 3.2
-    n = 100000
+    # the claim of the L-frequency comparison for D = 10 in Sec. 3.2, 10^6 draws each
+    n = N_DRAWS
     for CR in (0.5, 0.9):
         a = np.bincount(sample_exp_lengths(10, CR, n, seed=3), minlength=11)[1:]
         b = np.bincount(sample_nec_lengths(10, CR, n, seed=4), minlength=11)[1:]

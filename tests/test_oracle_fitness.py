@@ -121,3 +121,96 @@ def test_griewank_optimum_and_cosine_points(D):
     ref = float(np.sum(y * y)) / 4000.0 + 1.0 - (-1.0) ** D
     assert abs(oracle.fitness("griewank", y) - ref) <= 1e-13 * ref
     assert oracle.fitness_phi("griewank", y) >= oracle.fitness("griewank", y)
+
+
+# ---- Ackley's cancellation-free form and the tolerance scale ----------------
+
+def _ackley_mp(x, dps=60):
+    """Sec. 4's Ackley in the printed order, evaluated by mpmath at `dps`
+    decimal digits (an independent evaluation of the printed formula)."""
+    import mpmath as mp
+    with mp.workdps(dps):
+        D = len(x)
+        sq = mp.fsum(mp.mpf(float(v)) ** 2 for v in x)
+        cs = mp.fsum(mp.cos(2 * mp.pi * mp.mpf(float(v))) for v in x)
+        f = -20 * mp.exp(mp.mpf("-0.02") * mp.sqrt(sq / D)) - mp.exp(cs / D) + 20 + mp.e
+        return f
+
+
+@pytest.mark.parametrize("scale", [30.0, 1.0, 1e-3, 1e-6, 1e-9])
+@pytest.mark.parametrize("D", [1, 7, 1000])
+def test_ackley_against_high_precision(D, scale):
+    # relative accuracy down to f ~ 1e-10, where the printed order in double
+    # precision would keep no correct digit
+    rng = np.random.default_rng(int(D * 10 + scale * 7 % 97))
+    for _ in range(3):
+        x = rng.uniform(-scale, scale, D)
+        ref = _ackley_mp(x)
+        f = oracle.fitness("ackley", x)
+        assert abs(f - float(ref)) <= 4e-16 * float(ref)
+
+
+def test_ackley_near_nonzero_integers_against_high_precision():
+    rng = np.random.default_rng(5)
+    c = rng.integers(-20, 21, 50).astype(np.float64)
+    x = c + rng.uniform(-1e-7, 1e-7, 50)
+    ref = float(_ackley_mp(x))
+    assert abs(oracle.fitness("ackley", x) - ref) <= 4e-16 * ref
+
+
+def test_ackley_equals_printed_order_in_the_box():
+    # the two orders agree up to the printed order's cancellation error
+    rng = np.random.default_rng(9)
+    for D in (3, 100, 1000):
+        x = rng.uniform(-30, 30, D)
+        f = oracle.fitness("ackley", x)
+        assert abs(f - oracle.ackley_printed(x)) <= 4 * np.spacing(f)
+
+
+@pytest.mark.parametrize("D", [1, 10, 1000])
+def test_phi_is_f_for_sums_of_nonnegative_terms(D):
+    # the tolerance scale equals f itself where every term is >= 0: a scale
+    # that grew (a lost absolute value, an extra term) fails here
+    rng = np.random.default_rng(D)
+    o = rng.uniform(-4, 4, D)
+    for scale in (30.0, 1e-2, 1e-6):
+        x = rng.uniform(-scale, scale, D)
+        assert oracle.fitness_phi("ackley", x) == oracle.fitness("ackley", x)
+        assert oracle.fitness_phi("sphere", x) == oracle.fitness("sphere", x)
+        assert oracle.fitness_phi("rastrigin", x, o) == oracle.fitness("rastrigin", x, o)
+    assert oracle.fitness_phi("ackley", np.zeros(D)) == 0.0
+    for c in (1.0, -3.0):
+        ref = 20.0 * (1.0 - math.exp(-0.02 * abs(c)))
+        assert abs(oracle.fitness_phi("ackley", np.full(D, c)) - ref) <= 1e-14 * ref
+    if D >= 2:
+        Q = np.linalg.qr(rng.standard_normal((D, D)))[0]
+        x = rng.uniform(-100, 100, D)
+        assert oracle.fitness_phi("ellipsoid_rot", x, o, Q) == oracle.fitness("ellipsoid_rot", x, o, Q)
+
+
+@pytest.mark.parametrize("D", [2, 3, 50])
+def test_rosenbrock_phi_closed_points(D):
+    # Phi = sum 100 (|z_{j+1}| + z_j^2)^2 + (|z_j| + 1)^2 over the D - 1 pairs
+    rng = np.random.default_rng(D)
+    o = rng.uniform(-4, 4, D)
+    assert oracle.fitness_phi("rosenbrock", o, o) == 404.0 * (D - 1)         # z = 1
+    for c in (-2.0, 0.0, 3.0):   # z = c everywhere (exact for these c and o = 0)
+        z = np.full(D, c)
+        ref = (D - 1) * (100.0 * (abs(c) + c * c) ** 2 + (abs(c) + 1.0) ** 2)
+        assert oracle.fitness_phi("rosenbrock", z - 1.0, np.zeros(D)) == ref
+    x = rng.uniform(-5.12, 5.12, D)
+    z = x - o + 1.0
+    ref = float(np.sum(100.0 * (np.abs(z[1:]) + z[:-1] ** 2) ** 2 + (np.abs(z[:-1]) + 1.0) ** 2))
+    assert abs(oracle.fitness_phi("rosenbrock", x, o) - ref) <= 1e-13 * ref
+
+
+@pytest.mark.parametrize("D", [1, 2, 10, 500])
+def test_griewank_phi_closed_points(D):
+    j = np.arange(1, D + 1, dtype=np.float64)
+    assert oracle.fitness_phi("griewank", np.zeros(D)) == 2.0
+    x = 2.0 * np.pi * np.sqrt(j)      # every cosine is +1
+    ref = float(np.sum(x * x)) / 4000.0 + 2.0
+    assert abs(oracle.fitness_phi("griewank", x) - ref) <= 1e-13 * ref
+    y = np.pi * np.sqrt(j)            # every cosine is -1: |prod| = 1
+    ref = float(np.sum(y * y)) / 4000.0 + 2.0
+    assert abs(oracle.fitness_phi("griewank", y) - ref) <= 1e-13 * ref
