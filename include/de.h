@@ -208,6 +208,24 @@ de_status de_set_state(de_handle* h, int32_t run, const void* pop_host, const vo
  * run's state.  Asynchronous. */
 de_status de_masks(de_handle* h, int32_t run, int64_t gen, uint8_t* mask, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the masks
+ * de_masks returns, for a run that has no handle and no workspace.  `run`
+ * describes the run (N, D, CR, seed, xo, exp_impl are read; the rest is
+ * ignored) and run_index is its position in the handle whose draws it
+ * reproduces (0 for a single-run handle; [0, 2^24)).  The output is the
+ * bytes de_masks(h, run_index, gen, ...) writes for a handle built from the
+ * same description.  Needs D <= DE_MASKS_NOALLOC_MAX_D (else DE_E_INVALID).
+ * The call's run record and NEC threshold table live in a fixed 1 MiB
+ * device array inside the library, one per GPU, kept until the process
+ * ends; the call allocates nothing and rewrites every part of the array it
+ * reads.  Calls that overlap on one GPU (on different streams, or from
+ * different threads) share that array and race: order them.  Asynchronous;
+ * errors are read with de_last_error(NULL). */
+#define DE_MASKS_NOALLOC_MAX_D 131006
+de_status de_masks_noalloc(const de_run_desc* run, int32_t run_index, int64_t gen, uint8_t* mask,
+                           void* stream);
+
 /* Debug trace of one run, written by the production kernels for every later
  * generation (each overwrites the previous one).  All device pointers, each
  * may be NULL; all NULL switches tracing off.

@@ -27,7 +27,7 @@ WB = {"auto": 0, "whole": 1, "partial": 2}
 
 ABI_FUNCTIONS = ("de_workspace_size", "de_init", "de_generation", "de_evaluate", "de_best",
                  "de_get_state", "de_set_state", "de_trace", "de_profile", "de_profile_read",
-                 "de_graph", "de_masks", "de_last_error", "de_destroy")
+                 "de_graph", "de_masks", "de_masks_noalloc", "de_last_error", "de_destroy")
 
 
 class DEError(RuntimeError):
@@ -70,6 +70,7 @@ def lib():
         L.de_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
         L.de_graph.argtypes = [vp, i32]
         L.de_masks.argtypes = [vp, i32, i64, vp, vp]
+        L.de_masks_noalloc.argtypes = [C.POINTER(RunDesc), i32, i64, vp, vp]
         L.de_last_error.argtypes = [vp]
         L.de_last_error.restype = C.c_char_p
         L.de_destroy.argtypes = [vp]
@@ -107,6 +108,19 @@ def workspace_size(runs: list[dict]) -> int:
     if st != OK:
         raise DEError(st, lib().de_last_error(None).decode())
     return n.value
+
+
+def masks_noalloc(run: dict, gen: int, out, run_index: int = 0):
+    """Crossover masks of generation `gen` for a run without a handle (the
+    allocation-free entry point): `out` is a caller-owned N x D uint8 device
+    tensor."""
+    keep: list = []
+    d = _desc(run, keep)
+    st = lib().de_masks_noalloc(C.byref(d), int(run_index), int(gen),
+                                C.c_void_p(out.data_ptr()), _stream())
+    if st != OK:
+        raise DEError(st, lib().de_last_error(None).decode())
+    return out
 
 
 def _stream():

@@ -135,6 +135,9 @@ hipError_t launch_dirty_reset(const RunDev* runs, const RunDev& h, int run, uint
 // crossover masks of generation g (run generation number), N x D bytes
 hipError_t launch_masks(const RunDev* runs, const RunDev& h, int run, uint32_t g, uint8_t* out,
                         hipStream_t s);
+// record of a workspace-less mask call stored at dst, plus its NEC table at
+// rec.T when `table`
+hipError_t launch_masks_setup(RunDev* dst, const RunDev& rec, bool table, hipStream_t s);
 // rotated function: M pieces and weights from the caller's FP64 M; fitness of
 // N rows (the trials of the coming generation when `trials`, else the
 // population) into fit_dst or, when select, straight into greedy selection.

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -351,6 +352,37 @@ de_status capture_block(de_handle* h) {
   return DE_OK;
 }
 
+// ---- allocation-free mask calls ------------------------------------------
+// de_masks_noalloc keeps the run record and the NEC threshold table of its
+// call in this array instead of a workspace.  Each GPU holds its own copy
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy: it uses the device address hipGetSymbolAddress returns
+// for the current device, looked up once per device and kept.
+constexpr size_t kNoAllocBytes = size_t(1) << 20;
+constexpr size_t kNoAllocTableOff = 512;  // run record first, table after it
+static_assert(sizeof(RunDev) <= kNoAllocTableOff, "run record fits before the table");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;  // per device id; null until looked up
+
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (static_cast<int>(g_scratch_dev.size()) <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
 de_status check_run(de_handle* h, int32_t run) {
   if (!h) return fail(nullptr, DE_E_INVALID, "NULL handle");
   if (run < 0 || run >= h->n_runs) return fail(h, DE_E_INVALID, "run index out of range");
@@ -673,6 +705,52 @@ de_status de_masks(de_handle* h, int32_t run, int64_t gen, uint8_t* mask, void* 
   if (!mask) return fail(h, DE_E_INVALID, "mask is NULL");
   HIPCHECK(h, de::launch_masks(h->dev_runs, h->host[run], run, static_cast<uint32_t>(gen), mask,
                                static_cast<hipStream_t>(stream)));
+  return DE_OK;
+}
+
+de_status de_masks_noalloc(const de_run_desc* run, int32_t run_index, int64_t gen, uint8_t* mask,
+                           void* stream) {
+  if (!run) return fail(nullptr, DE_E_INVALID, "run is NULL");
+  const de_run_desc& d = *run;
+  if (d.N < 4 || d.N >= (1 << 21)) return fail(nullptr, DE_E_INVALID, "N must satisfy 4 <= N < 2^21");
+  if (d.D < 1 || d.D > DE_MASKS_NOALLOC_MAX_D)
+    return fail(nullptr, DE_E_INVALID,
+                "D must satisfy 1 <= D <= DE_MASKS_NOALLOC_MAX_D (the threshold table of the "
+                "call must fit in the library's static scratch)");
+  if (!(d.CR >= 0.0 && d.CR <= 1.0)) return fail(nullptr, DE_E_INVALID, "CR must lie in [0, 1]");
+  if (d.xo < DE_XO_BIN || d.xo > DE_XO_NEC) return fail(nullptr, DE_E_INVALID, "unknown crossover");
+  if (d.exp_impl < DE_EXP_LANE || d.exp_impl > DE_EXP_SCAN)
+    return fail(nullptr, DE_E_INVALID, "unknown exp_impl");
+  if (run_index < 0 || run_index >= (1 << 24))
+    return fail(nullptr, DE_E_INVALID, "run_index must lie in [0, 2^24)");
+  if (gen < 1 || gen >= 0xFFFFFFFFll) return fail(nullptr, DE_E_INVALID, "gen must be in [1, 2^32 - 1)");
+  if (!mask) return fail(nullptr, DE_E_INVALID, "mask is NULL");
+  static_assert(kNoAllocTableOff + 8 * (DE_MASKS_NOALLOC_MAX_D + 2) <= kNoAllocBytes,
+                "largest table fits in the scratch");
+  void* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+  // the run record a handle would hold for this run, reduced to what the
+  // mask kernels read
+  RunDev R;
+  std::memset(&R, 0, sizeof R);
+  R.N = d.N; R.D = d.D; R.ld = up64(d.D, 32);
+  R.CR = d.CR; R.F = d.F; R.Ff = static_cast<float>(d.F);
+  R.inv_ln_cr = (d.CR > 0.0 && d.CR < 1.0) ? 1.0 / std::log(d.CR) : 0.0;
+  R.thr = threshold(d.CR);
+  R.key0 = static_cast<uint32_t>(d.seed);
+  R.key1 = static_cast<uint32_t>(d.seed >> 32);
+  R.run_id = static_cast<uint32_t>(run_index);
+  R.fn = d.fn; R.xo = d.xo; R.exp_impl = d.exp_impl; R.dtype = d.dtype;
+  R.T = reinterpret_cast<const uint64_t*>(static_cast<char*>(base) + kNoAllocTableOff);
+  RunDev* rec = static_cast<RunDev*>(base);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the table is read only by NEC with 0 < CR < 1 (the other cases need no table)
+  const bool table = d.xo == DE_XO_NEC && R.inv_ln_cr != 0.0;
+  e = de::launch_masks_setup(rec, R, table, s);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "mask set-up launch");
+  e = de::launch_masks(rec, R, 0, static_cast<uint32_t>(gen), mask, s);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "mask launch");
   return DE_OK;
 }
 

@@ -82,6 +82,55 @@ __global__ void __launch_bounds__(64) k_masks_job(const RunDev* __restrict__ run
   }
 }
 
+// Number of words w with (w + 1/2) 2^-32 < p: ceil(p 2^32 - 1/2) clamped to
+// [0, 2^32] (the scaling is exact, the subtraction is one rounding).
+__device__ __forceinline__ uint64_t word_threshold(double p) {
+  const double v = ceil(ldexp(p, 32) - 0.5);
+  if (!(v > 0.0)) return 0;
+  if (v >= 4294967296.0) return 4294967296ull;
+  return static_cast<uint64_t>(v);
+}
+
+// Set-up of a mask call that has no workspace: stores the run record at
+// `dst` and, when `table`, the NEC thresholds at rec.T: T[0] = 2^32,
+// T[k] = word_threshold(CR^(k-1)) for k = 1..D with the power taken as a
+// running FP64 product (the order the handle's own table is built in), and
+// T[D+1] = 0.  For CR < 1 the product only decreases, so once a threshold is
+// 0 every later one is: one lane walks the non-zero prefix and the block
+// writes the zeros after it.
+__global__ void __launch_bounds__(256) k_masks_setup(RunDev rec, RunDev* __restrict__ dst,
+                                                     int table) {
+  __shared__ int64_t kend;
+  uint64_t* T = const_cast<uint64_t*>(rec.T);
+  const int64_t D = rec.D;
+  if (threadIdx.x == 0) {
+    *dst = rec;
+    int64_t k = 1;
+    if (table) {
+      T[0] = 4294967296ull;
+      double t = 1.0;
+      for (; k <= D; ++k) {
+        if (k > 1) t = t * rec.CR;
+        const uint64_t v = word_threshold(t);
+        T[k] = v;
+        if (v == 0) {
+          ++k;
+          break;
+        }
+      }
+    }
+    kend = k;
+  }
+  __syncthreads();
+  if (table)
+    for (int64_t k = kend + threadIdx.x; k <= D + 1; k += blockDim.x) T[k] = 0;
+}
+
+hipError_t launch_masks_setup(RunDev* dst, const RunDev& rec, bool table, hipStream_t s) {
+  hipLaunchKernelGGL(k_masks_setup, dim3(1), dim3(256), 0, s, rec, dst, table ? 1 : 0);
+  return hipGetLastError();
+}
+
 hipError_t launch_masks(const RunDev* runs, const RunDev& h, int run, uint32_t g, uint8_t* out,
                         hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>((h.N + 3) / 4);

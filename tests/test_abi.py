@@ -92,3 +92,20 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.de_evaluate(None, 0, None, 0, None, None) == de.E_INVALID
     assert lib.de_profile(None, 1) == de.E_INVALID
     lib.de_destroy(None)
+
+
+def test_masks_noalloc_argument_checks(lib):
+    # rejected on the host before any device work (no GPU needed)
+    dummy = C.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    cases = [(good(xo="nec", D=131007), 0, 1), (good(N=3), 0, 1), (good(CR=2.0), 0, 1),
+             (good(), -1, 1), (good(), 1 << 24, 1), (good(), 0, 0), (good(), 0, 1 << 32)]
+    for cfg, ri, gen in cases:
+        keep: list = []
+        d = de._desc(cfg, keep)
+        assert lib.de_masks_noalloc(C.byref(d), ri, gen, dummy, None) == de.E_INVALID
+    keep = []
+    d = de._desc(good(), keep)
+    assert lib.de_masks_noalloc(C.byref(d), 0, 1, None, None) == de.E_INVALID
+    assert lib.de_masks_noalloc(None, 0, 1, dummy, None) == de.E_INVALID
+    msg = lib.de_last_error(None).decode()
+    assert "NULL" in msg
