@@ -78,7 +78,7 @@ int64_t oracle_skip(int64_t r, const int64_t* excl, int n_excl) {
   return r;
 }
 
-/* DE/rand/1 index choice (Alg 1 line 6, Eq 1): base r0 and difference pair
+/* DE/rand/1 index choice (Alg 1, Eq 1): base r0 and difference pair
  * r1, r2, all distinct and different from i.  Uses words 0..2 of the IDX block. */
 void oracle_indices(uint64_t seed, uint32_t run, int64_t N, uint32_t g, int64_t i, int64_t r[3]) {
   uint32_t w0 = oracle_word(seed, run, OR_TAG_IDX, g, (uint32_t)i, 0, 0);
@@ -93,7 +93,7 @@ void oracle_indices(uint64_t seed, uint32_t run, int64_t N, uint32_t g, int64_t 
 }
 
 /* A keyed pseudo-random permutation of [0, N) for generation g, used where
- * the paper shuffles (Alg 2 line 5, Alg 5).  The paper names no shuffling
+ * the paper shuffles (Alg 2, Alg 5).  The paper names no shuffling
  * method; this reading takes a balanced eight-round Feistel network (Luby and
  * Rackoff) on m-bit integers, m even with 2^m >= N (m >= 2), and walks the
  * cycle (Black and Rogaway) until the image falls inside [0, N).  Round r
@@ -470,7 +470,7 @@ oracle_state* oracle_create(const oracle_desc* d) {
     }
   }
   s->d.shift = NULL;
-  /* Alg 2 lines 2-3: initialise the population matrix and evaluate it. */
+  /* Alg 2, before its loop: initialise the population matrix and evaluate it. */
   for (int64_t i = 0; i < N; ++i)
     for (int64_t j = 0; j < D; ++j)
       s->x[i * D + j] = init_value(d, OR_TAG_INIT, (uint32_t)i, j, d->lo, d->hi);
@@ -491,18 +491,18 @@ void oracle_destroy(oracle_state* s) {
   free(s->tr); free(s->mask); free(s->rot); free(s);
 }
 
-/* Storage row of position k in generation g: with the shuffle of Alg 2
- * line 5 the individuals are reordered by pi_g before anything else, so
+/* Storage row of position k in generation g: with the shuffle of Alg 2 the
+ * individuals are reordered by pi_g before anything else, so
  * position k holds the individual stored in row pi_g(k); without it, k. */
 static int64_t row_of(const oracle_desc* d, uint32_t g, int64_t k) {
   return d->shuffle ? oracle_permute(d->seed, (uint32_t)d->run, OR_TAG_SHUFFLE, g, d->N, k) : k;
 }
 
-/* Generation g's trial for position i from population x (Alg 2 lines 6-10
- * for one row): choose r0, r1, r2, build the crossover mask first (line 7),
+/* Generation g's trial for position i from population x (the body of Alg 2's
+ * loop for one row): choose r0, r1, r2, build the crossover mask first,
  * copy the individual at position i and overwrite the masked elements with
- * the DE/rand/1 mutant x_r0 + F (x_r1 - x_r2) (lines 8-9, Eq 1), then
- * evaluate (line 10).  Draws are addressed by position; t[0..2] are the
+ * the DE/rand/1 mutant x_r0 + F (x_r1 - x_r2) (Eq 1), then
+ * evaluate.  Draws are addressed by position; t[0..2] are the
  * storage rows of r0, r1, r2. */
 static void build_trial(const oracle_state* s, const double* x, uint32_t g, int64_t i,
                         int64_t* t, uint8_t* m, double* ui, double* fu) {
@@ -542,9 +542,9 @@ static void build_trial(const oracle_state* s, const double* x, uint32_t g, int6
   t[0] = r[0]; t[1] = r[1]; t[2] = r[2]; t[3] = jrand; t[4] = L; t[5] = 0;
 }
 
-/* One generation, Alg 2 lines 5-14: every trial is built from generation
- * g-1, then u_i replaces x_i wherever f(u_i) < f_i strictly (lines 11-14,
- * Alg 1 line 10).  The shuffle of line 5 is a relabelling: position k works
+/* One generation of Alg 2: every trial is built from generation
+ * g-1, then u_i replaces x_i wherever f(u_i) < f_i strictly (Alg 2's
+ * selection, Alg 1's replacement test).  The shuffle is a relabelling: position k works
  * on storage row pi_g(k) and its result goes back to that row, so the
  * population is never moved (see row_of).  Trace arrays are kept by row. */
 static void one_generation(oracle_state* s) {

@@ -1,5 +1,5 @@
 """Pins for the oracle's base-index schemes (Alg 3, 4, 5 with Alg 6's
-offsets), its keyed permutation and the per-generation shuffle (Alg 2 line 5):
+offsets), its keyed permutation and the per-generation shuffle (Alg 2):
 bijection by brute force, uniformity over many generations, the structural
 property each algorithm states, the shuffle as "reorder, then run the plain
 generation", and convergence against a textbook DE that uses numpy's own
@@ -113,7 +113,7 @@ def test_alg5_permutation_base_is_a_permutation():
 @pytest.mark.parametrize("base", ["classic", "offset", "perm"])
 @pytest.mark.parametrize("xo", ["bin", "nec"])
 def test_shuffle_is_reorder_then_plain_generation(base, xo):
-    """Alg 2 line 5 then lines 6-14: with the shuffle on, the generation equals
+    """Alg 2's shuffle, then the rest of its generation: with the shuffle on, the generation equals
     the plain one run on the population reordered by pi_g, written back to
     the rows the individuals came from."""
     N, D, seed = 24, 9, 6
