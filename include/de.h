@@ -128,12 +128,15 @@ typedef struct {
   int32_t exp_impl; /* de_exp_impl, DE_XO_EXP only */
   int32_t tpr;      /* lanes per individual in the generation kernel: 0 = chosen
                        from D, N and dtype; 64, 128, 256, 512 or 1024 forces
-                       it (batched: 0 or 64).  Indices, masks and trial rows
-                       do not depend on it; fitness sums only change their
-                       rounding order. */
+                       it (batched: 0, 64, 128 or 256, the same for every
+                       run of the batch).  Exp and NEC rows of more than
+                       4096 elements are streamed rather than held in
+                       registers (256 lanes unless forced).  Indices, masks and
+                       trial rows do not depend on it; fitness sums only
+                       change their rounding order. */
   int32_t base;     /* de_base */
   int32_t shuffle;  /* 1: shuffle the individuals at the start of every
-                       generation (Alg 2 line 5), 0: do not.  Applied as a
+                       generation (the shuffle of Alg 2), 0: do not.  Applied as a
                        relabelling: position k of generation g works on the
                        individual stored in row pi_g(k) and writes its result
                        back there, so rows never move; draws are addressed by
@@ -146,7 +149,12 @@ typedef struct {
                        which the two buffers differ (exp and NEC; binomial
                        rows are always written whole).  Results do not depend
                        on it. */
-  int32_t reserved; /* must be 0 */
+  int32_t tile;     /* split-bf16 product tile (ELLIPSOID_ROT with DE_MM_BF16X3 /
+                       DE_MM_BF16X6): 0 = the default, 1..3 = the shapes the
+                       tuner chooses among (de_rot_tiles); results do not
+                       depend on it except between the two matrix-core forms,
+                       which may round the k-sum differently.  Must be 0
+                       otherwise. */
   double lo, hi;    /* initial population drawn uniformly from [lo, hi]^D, lo < hi */
   double olo, ohi;  /* shift o drawn uniformly from [olo, ohi]^D when shift == NULL */
   uint64_t seed;    /* Philox key */
@@ -248,11 +256,14 @@ de_status de_trace(de_handle* h, int32_t run, int64_t* idx, uint8_t* mask, void*
 de_status de_profile(de_handle* h, int32_t enable);
 de_status de_profile_read(de_handle* h, double* main_ms, int64_t* main_launches);
 
-/* Graph replay: while enabled, de_generation runs whole blocks of 64
+/* Graph replay: with enable = 1, de_generation runs whole blocks of 64
  * generations (with their best-so-far update) by launching one HIP graph,
- * captured on first use, instead of launching each kernel; the remaining
- * generations of a call are launched directly.  Results are identical either
- * way.  Ignored while kernel timing (de_profile) is on. */
+ * captured on first use, instead of launching each kernel; enable = B > 1
+ * captures blocks of B generations (the best-so-far is updated after every
+ * 64 of them and after the last); 0 switches graphs off.  Generations left
+ * over from whole blocks are launched directly.  Results are identical either
+ * way.  Ignored while kernel timing (de_profile) is on.  DE_E_INVALID for a
+ * negative enable. */
 de_status de_graph(de_handle* h, int32_t enable);
 
 /* Message for the last failed call on h (or on a NULL handle); valid until

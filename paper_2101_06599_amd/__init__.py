@@ -41,7 +41,7 @@ class RunDesc(C.Structure):
     _fields_ = [("N", C.c_int64), ("D", C.c_int64), ("F", C.c_double), ("CR", C.c_double),
                 ("xo", C.c_int32), ("fn", C.c_int32), ("dtype", C.c_int32), ("mm", C.c_int32),
                 ("exp_impl", C.c_int32), ("tpr", C.c_int32), ("base", C.c_int32),
-                ("shuffle", C.c_int32), ("wb", C.c_int32), ("reserved", C.c_int32),
+                ("shuffle", C.c_int32), ("wb", C.c_int32), ("tile", C.c_int32),
                 ("lo", C.c_double), ("hi", C.c_double), ("olo", C.c_double), ("ohi", C.c_double),
                 ("seed", C.c_uint64), ("shift", C.c_void_p), ("rot", C.c_void_p)]
 
@@ -92,7 +92,7 @@ def _desc(run: dict, keep: list) -> RunDesc:
         dtype=DTYPE[run.get("dtype", "fp64")], mm=MM[run.get("mm", "fp64")],
         exp_impl=EXP_IMPL[run.get("exp_impl", "lane")], tpr=int(run.get("tpr", 0)),
         base=BASE[run.get("base", "classic")], shuffle=1 if run.get("shuffle") else 0,
-        wb=WB[run.get("wb", "auto")],
+        wb=WB[run.get("wb", "auto")], tile=int(run.get("tile", 0)),
         lo=float(run.get("lo", -100.0)), hi=float(run.get("hi", 100.0)),
         olo=float(run.get("olo", 0.0)), ohi=float(run.get("ohi", 0.0)),
         seed=int(run.get("seed", 0)),
@@ -141,9 +141,17 @@ class DE:
         self.torch = torch
         self.device = torch.device(device)
         self.runs = [dict(r) for r in runs]
-        if tune and len(self.runs) == 1 and not self.runs[0].get("tpr"):
-            from .tune import tune_tpr
-            self.runs[0]["tpr"], self.tuning = tune_tpr(self.runs[0])
+        if tune and not any(r.get("tpr") for r in self.runs):
+            from .tune import tune_batched, tune_tpr
+            if len(self.runs) == 1 and self.runs[0].get("fn") == "ellipsoid_rot" and \
+                    self.runs[0].get("mm") in ("bf16x3", "bf16x6"):
+                from .tune import tune_rot_tile
+                self.runs[0]["tile"], self.tuning = tune_rot_tile(self.runs[0])
+            elif len(self.runs) == 1:
+                self.runs[0]["tpr"], self.tuning = tune_tpr(self.runs[0])
+            else:
+                t, self.tuning = tune_batched(self.runs)
+                self.runs = [dict(r, tpr=t) for r in self.runs]
         self._keep: list = []
         descs = [_desc(r, self._keep) for r in self.runs]
         self._arr = (RunDesc * len(descs))(*descs)
@@ -191,6 +199,15 @@ class DE:
         self._check(lib().de_best(self._h, run, C.byref(f), C.byref(idx), C.byref(g),
                                   x.ctypes.data_as(C.c_void_p), _stream()), self._h)
         return f.value, idx.value, g.value, x
+
+    def fitness(self, run: int = 0):
+        """Current fitness of every individual of a run (host array)."""
+        N = int(self.runs[run]["N"])
+        fit = np.zeros(N, self._np_dtype(run))
+        g = C.c_int64(0)
+        self._check(lib().de_get_state(self._h, run, None, fit.ctypes.data_as(C.c_void_p),
+                                       C.byref(g), _stream()), self._h)
+        return fit
 
     def state(self, run: int = 0):
         N, D = int(self.runs[run]["N"]), int(self.runs[run]["D"])
@@ -248,9 +265,11 @@ class DE:
                     self._h)
         return out
 
-    def graph(self, enable: bool = True):
-        """Replay captured 64-generation graphs in generation() (same results)."""
-        self._check(lib().de_graph(self._h, 1 if enable else 0), self._h)
+    def graph(self, enable=True):
+        """Replay captured graphs in generation() (same results): True for
+        blocks of 64 generations, an int n > 1 for blocks of n, False off."""
+        n = (1 if enable else 0) if isinstance(enable, bool) else int(enable)
+        self._check(lib().de_graph(self._h, n), self._h)
 
     def close(self):
         if getattr(self, "_h", None):

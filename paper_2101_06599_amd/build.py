@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libde.so")
-SOURCES = ["de_runtime.hip", "k_generation.hip", "k_misc.hip", "k_rot.hip", "k_masks.hip"]
+SOURCES = ["de_runtime.hip", "k_generation.hip", "k_stream.hip", "k_misc.hip", "k_rot.hip",
+           "k_masks.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -85,7 +85,7 @@ __device__ __forceinline__ void pick_indices(uint4 b, uint32_t N, uint32_t i, ui
 }
 
 // Keyed pseudo-random permutation of [0, N) for generation g (the shuffle of
-// Alg 2 line 5 and Alg 5's base permutation): an eight-round balanced Feistel
+// Alg 2 and Alg 5's base permutation): an eight-round balanced Feistel
 // network on m-bit integers (m even, 2^m >= N, m >= 2) whose round r mixes
 // the right half with K_r, word r%4 of Philox block r/4 (individual 0); the
 // image is walked through the permutation until it lands in [0, N).  A walk
@@ -190,8 +190,12 @@ __device__ __forceinline__ uint32_t nec_length(const RunDev& P, uint32_t w) {
 
 // Classic exponential crossover length (Alg 8), draws taken one at a time in
 // order: draw e (EXP block e/4, word e%4) decides whether element e+2 joins.
+// With CR = 1 every draw passes (L = D), with CR = 0 the first one fails
+// (L = 1): both lengths are known without drawing.
 __device__ __forceinline__ uint32_t exp_length_serial(const RunDev& P, uint32_t g, uint32_t i) {
   const uint32_t D = static_cast<uint32_t>(P.D);
+  if (P.thr >= 4294967296ull) return D;
+  if (P.thr == 0) return 1;
   uint32_t L = 1;
   uint4 b = make_uint4(0, 0, 0, 0);
   for (uint32_t e = 0; L < D; ++e) {
@@ -206,6 +210,8 @@ __device__ __forceinline__ uint32_t exp_length_serial(const RunDev& P, uint32_t 
 // one Philox block (4 draws) and the lowest failing draw ends the run.
 __device__ __forceinline__ uint32_t exp_length_scan(const RunDev& P, uint32_t g, uint32_t i) {
   const uint32_t D = static_cast<uint32_t>(P.D);
+  if (P.thr >= 4294967296ull) return D;
+  if (P.thr == 0) return 1;
   const uint32_t lane = __lane_id();
   for (uint32_t base = 0; base + 1 < D; base += 256) {
     const uint32_t e0 = base + 4 * lane;

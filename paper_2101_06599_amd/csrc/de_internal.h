@@ -50,7 +50,7 @@ struct alignas(64) RunDev {
   int32_t fn, xo, exp_impl, dtype, mm;
   int32_t base, shuffle;  // base index scheme; per-generation shuffle on/off
   int32_t partial_wb;     // winners write only the chunks their buffers differ in
-  int32_t pad2;
+  int32_t tile;           // split-bf16 product tile shape (0 = default)
   void* X[2];             // double-buffered populations, N x ld
   void* fit;              // N fitness values (dtype)
   uint8_t* flags;         // 2 x N: flags[(g & 1) * N + i] = buffer holding row i after gen g
@@ -72,7 +72,8 @@ struct alignas(64) RunDev {
   void* part;             // N x ntile partial sums (dtype)
   int32_t ntile, pad1;
   void* stage;            // N x ld staging rows (rotated evaluate)
-  void* apc;              // split-bf16 modes: pieces of U - o, P x N x ldk bf16
+  void* apc;              // split-bf16 modes: pieces of U - o, P planes of N x ldk bf16
+  double* bpart;          // D FP64 terms w_k z_k^2 of the best row's recomputed fitness
   // trace (tests)
   int64_t* tr_idx;
   uint8_t* tr_mask;
@@ -102,6 +103,7 @@ struct GenLaunch {
   int32_t tpr;            // threads per row
   GenNo gnew;             // handle generation being computed
   hipStream_t s;
+  bool stream;            // exp / NEC rows streamed instead of held in registers
 };
 
 __host__ __device__ inline uint32_t run_gen(const RunDev& P, uint32_t gnew) {
@@ -118,6 +120,8 @@ hipError_t launch_best_flush(const RunDev* runs, int n_runs, GenNo gfirst, int c
 // *base = v, or *base += v (graph bookkeeping)
 hipError_t launch_gen_base(uint32_t* base, uint32_t v, bool add, hipStream_t s);
 hipError_t launch_generation(const GenLaunch& L, int fn, int xo, int dtype, bool batched);
+// exp / NEC rows streamed (single runs; fn separable or Ackley / Griewank)
+hipError_t launch_generation_stream(const GenLaunch& L, int fn, int xo, int dtype);
 hipError_t launch_pexp_trial(const RunDev* runs, const RunDev& h, int run, GenNo gnew,
                              hipStream_t s);
 hipError_t launch_eval_select(const RunDev* runs, const RunDev& h, int run, GenNo gnew,

@@ -28,7 +28,7 @@ struct de_handle {
   BestState* best = nullptr;
   double* scratch_f64 = nullptr;     // one FP64 for de_best
   uint32_t* gbase = nullptr;         // device generation base read by graph replays
-  bool graph_on = false;             // replay captured blocks of kHist generations
+  int32_t graph_block = 0;           // generations per captured graph (0: no graphs)
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
   bool base_valid = false;           // device *gbase equals base_value
@@ -38,6 +38,7 @@ struct de_handle {
   std::vector<uint2> rowmap_host;
   std::vector<std::vector<uint64_t>> tables;  // host copies of the NEC tables
   std::vector<int> tpr;
+  std::vector<char> stream;          // run uses the streaming exp / NEC kernel
   uint32_t done = 0;                 // generations completed by the handle
   int pending = 0;                   // of which the best-so-far is not yet updated
   std::string err;
@@ -91,7 +92,7 @@ struct Layout {
   size_t total = 0;
   size_t runs_off = 0, best_off = 0, scratch_off = 0, rowmap_off = 0;
   struct Run {
-    size_t X0, X1, fit, flags, dirty, o, T, hist, mins, w, B[3], part, stage, apc;
+    size_t X0, X1, fit, flags, dirty, o, T, hist, mins, w, B[3], part, stage, apc, bp;
     int64_t ld, ldk, ntile;
   };
   std::vector<Run> r;
@@ -130,10 +131,14 @@ de_status validate(const de_run_desc* runs, int32_t n_runs, std::string& msg) {
     if (d.base < DE_BASE_CLASSIC || d.base > DE_BASE_PERM) return bad("unknown base scheme");
     if (d.shuffle != 0 && d.shuffle != 1) return bad("shuffle must be 0 or 1");
     if (d.wb < 0 || d.wb > 2) return bad("wb must be 0, 1 or 2");
-    if (d.reserved != 0) return bad("reserved must be 0");
+    if (d.tile < 0 || d.tile > 3) return bad("tile must be 0, 1, 2 or 3");
+    if (d.tile != 0 && !(d.fn == DE_FN_ELLIPSOID_ROT && (d.mm == DE_MM_BF16X3 || d.mm == DE_MM_BF16X6)))
+      return bad("tile applies to the split-bf16 rotated product only");
     if (d.tpr != 0 && d.tpr != 64 && d.tpr != 128 && d.tpr != 256 && d.tpr != 512 && d.tpr != 1024)
       return bad("tpr must be 0, 64, 128, 256, 512 or 1024");
-    if (n_runs > 1 && d.tpr != 0 && d.tpr != 64) return bad("batched runs use tpr 0 or 64");
+    if (n_runs > 1 && d.tpr != 0 && d.tpr != 64 && d.tpr != 128 && d.tpr != 256)
+      return bad("batched runs use tpr 0, 64, 128 or 256");
+    if (n_runs > 1 && d.tpr != runs[0].tpr) return bad("the runs of a batch share one tpr");
     if (is_shifted(d.fn) && !d.shift &&
         !(std::isfinite(d.olo) && std::isfinite(d.ohi) && d.olo <= d.ohi))
       return bad("need finite olo <= ohi when shift is NULL");
@@ -195,17 +200,18 @@ Layout layout(const de_run_desc* runs, int32_t n_runs) {
     q.mins = bump(cur, sizeof(de::GenMin) * de::kHist);
     q.ldk = 0;
     q.ntile = 0;
-    q.w = q.part = q.stage = q.apc = 0;
+    q.w = q.part = q.stage = q.apc = q.bp = 0;
     q.B[0] = q.B[1] = q.B[2] = 0;
     if (d.fn == DE_FN_ELLIPSOID_ROT) {
       q.ldk = up64(d.D, 32);
       q.ntile = (d.D + mm_tile_n(d.mm) - 1) / mm_tile_n(d.mm);
-      const int64_t rows_pad = up64(d.D, 128);
+      const int64_t rows_pad = up64(d.D, 256);  // M rows: whole tiles of the widest product
       q.w = bump(cur, s * d.D);
       for (int p = 0; p < mm_pieces(d.mm); ++p)
         q.B[p] = bump(cur, static_cast<size_t>(mm_elem(d.mm)) * rows_pad * q.ldk);
       q.part = bump(cur, s * d.N * q.ntile);
       q.stage = bump(cur, pop);
+      q.bp = bump(cur, sizeof(double) * d.D);
       if (d.mm == DE_MM_BF16X3 || d.mm == DE_MM_BF16X6)
         q.apc = bump(cur, static_cast<size_t>(2) * mm_pieces(d.mm) * d.N * q.ldk);
     }
@@ -215,7 +221,7 @@ Layout layout(const de_run_desc* runs, int32_t n_runs) {
 }
 
 int pick_tpr(const de_run_desc& d, bool batched) {
-  if (batched) return 64;
+  if (batched) return d.tpr == 0 ? 64 : d.tpr;
   if (d.tpr != 0) return d.tpr;
   // Measured defaults (MI355X): a row held in registers by as few lanes as
   // fit; rows of up to 1024 elements take 128 lanes (2 chunks each) where the
@@ -274,7 +280,8 @@ de_status generation_launches(de_handle* h, hipStream_t s, de::GenNo gnew) {
     add_pair_count(h, 1);
   };
   if (h->batched) {
-    de::GenLaunch L{h->dev_runs, h->host.data(), 0, h->rowmap, h->total_rows, 64, gnew, s};
+    de::GenLaunch L{h->dev_runs, h->host.data(), 0, h->rowmap, h->total_rows, h->tpr[0], gnew, s,
+                    false};
     mark();
     HIPCHECK(h, de::launch_generation(L, de::FN_ANY, de::XO_ANY, h->dtype, true));
     mark();
@@ -287,7 +294,7 @@ de_status generation_launches(de_handle* h, hipStream_t s, de::GenNo gnew) {
         if (job) {
           HIPCHECK(h, de::launch_pexp_trial(h->dev_runs, H, r, gnew, s));
         } else {
-          de::GenLaunch L{h->dev_runs, h->host.data(), r, nullptr, d.N, h->tpr[r], gnew, s};
+          de::GenLaunch L{h->dev_runs, h->host.data(), r, nullptr, d.N, h->tpr[r], gnew, s, false};
           HIPCHECK(h, de::launch_generation(L, de::FN_NONE, d.xo, d.dtype, false));
         }
         mark();
@@ -301,9 +308,11 @@ de_status generation_launches(de_handle* h, hipStream_t s, de::GenNo gnew) {
         mark();
         HIPCHECK(h, de::launch_eval_select(h->dev_runs, H, r, gnew, s));
       } else {
-        de::GenLaunch L{h->dev_runs, h->host.data(), r, nullptr, d.N, h->tpr[r], gnew, s};
+        de::GenLaunch L{h->dev_runs, h->host.data(), r, nullptr, d.N, h->tpr[r], gnew, s,
+                        h->stream[r] != 0};
         mark();
-        HIPCHECK(h, de::launch_generation(L, d.fn, d.xo, d.dtype, false));
+        if (L.stream) HIPCHECK(h, de::launch_generation_stream(L, d.fn, d.xo, d.dtype));
+        else HIPCHECK(h, de::launch_generation(L, d.fn, d.xo, d.dtype, false));
         mark();
       }
     }
@@ -320,28 +329,37 @@ de_status one_generation(de_handle* h, hipStream_t s) {
   return DE_OK;
 }
 
-// Captures kHist generations, their best-so-far update and the advance of the
-// device generation base into one graph (on a private stream; the graph is
-// then launched on the caller's stream).  Generation numbers inside are
-// *gbase + 1 .. *gbase + kHist.
+// Captures B = graph_block generations, the best-so-far update after every
+// kHist of them and after the last, and the advance of the device generation
+// base into one graph (on a private stream; the graph is then launched on the
+// caller's stream).  Generation numbers inside are *gbase + 1 .. *gbase + B.
 de_status capture_block(de_handle* h) {
   if (!h->cap_stream) HIPCHECK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   hipStream_t cs = h->cap_stream;
+  const int B = h->graph_block;
   HIPCHECK(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   de_status st = DE_OK;
-  for (int k = 1; k <= de::kHist && st == DE_OK; ++k)
-    st = generation_launches(h, cs, de::GenNo{static_cast<uint32_t>(k), 0, h->gbase});
   hipError_t e = hipSuccess;
-  if (st == DE_OK)
-    e = de::launch_best_flush(h->dev_runs, h->n_runs, de::GenNo{1, 0, h->gbase}, de::kHist, cs);
-  if (st == DE_OK && e == hipSuccess) e = de::launch_gen_base(h->gbase, de::kHist, true, cs);
+  for (int k = 1; k <= B && st == DE_OK && e == hipSuccess; ++k) {
+    st = generation_launches(h, cs, de::GenNo{static_cast<uint32_t>(k), 0, h->gbase});
+    if (st == DE_OK && (k % de::kHist == 0 || k == B)) {
+      const int cnt = k % de::kHist == 0 ? de::kHist : k % de::kHist;
+      e = de::launch_best_flush(h->dev_runs, h->n_runs,
+                                de::GenNo{static_cast<uint32_t>(k - cnt + 1), 0, h->gbase}, cnt, cs);
+    }
+  }
+  if (st == DE_OK && e == hipSuccess)
+    e = de::launch_gen_base(h->gbase, static_cast<uint32_t>(B), true, cs);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(cs, &g);
   if (st != DE_OK) {
     if (g) (void)hipGraphDestroy(g);
     return st;
   }
-  if (e != hipSuccess) return hip_fail(h, e, "launch during graph capture");
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(h, e, "launch during graph capture");
+  }
   if (e2 != hipSuccess) return hip_fail(h, e2, "hipStreamEndCapture");
   e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -443,7 +461,7 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
     R.key1 = static_cast<uint32_t>(d.seed >> 32);
     R.run_id = static_cast<uint32_t>(r);
     R.fn = d.fn; R.xo = d.xo; R.exp_impl = d.exp_impl; R.dtype = d.dtype; R.mm = d.mm;
-    R.base = d.base; R.shuffle = d.shuffle;
+    R.base = d.base; R.shuffle = d.shuffle; R.tile = d.tile;
     R.X[0] = ws + q.X0;
     R.X[1] = ws + q.X1;
     R.fit = ws + q.fit;
@@ -464,6 +482,7 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
       R.ntile = static_cast<int32_t>(q.ntile);
       R.stage = ws + q.stage;
       R.apc = q.apc ? ws + q.apc : nullptr;
+      R.bpart = reinterpret_cast<double*>(ws + q.bp);
     }
     // NEC thresholds: T[k] = #words below CR^(k-1), the power taken as a
     // running FP64 product; T[D+1] = 0 ends the search.
@@ -489,6 +508,22 @@ de_status de_init(de_handle** out, const de_run_desc* runs, int32_t n_runs, void
     h->host[r].partial_wb = runs[r].wb == 2 ||
                             (runs[r].wb == 0 && (pop_bytes > (size_t(48) << 20) ||
                                                  runs[r].fn == DE_FN_ELLIPSOID_ROT));
+  // Exp and NEC rows longer than 4096 elements (rows the register-cached
+  // kernel would need 512 or more lanes for) are streamed: the trial differs
+  // from the parent only in its run, so no copy of the row is kept.  The
+  // choice depends on the run's shape only, never on the write-back mode.
+  // 256 lanes per row unless the descriptor asks for another width (measured
+  // on MI355X, D = 10^4 N = 8192 FP32 NEC: 64 lanes 95 us, 128 90, 256 89,
+  // 512 113, 1024 196 per generation).
+  h->stream.assign(n_runs, 0);
+  for (int r = 0; r < n_runs; ++r) {
+    const de_run_desc& d = runs[r];
+    const bool runs_xo = d.xo == DE_XO_NEC || (d.xo == DE_XO_EXP && d.exp_impl != DE_EXP_JOB);
+    if (!h->batched && runs_xo && d.fn != DE_FN_ELLIPSOID_ROT && d.D > 4096) {
+      h->stream[r] = 1;
+      h->tpr[r] = d.tpr == 0 ? 256 : d.tpr;
+    }
+  }
   h->single_kernel = true;
   for (int r = 0; r < n_runs; ++r)
     if (runs[r].fn == DE_FN_ELLIPSOID_ROT || (runs[r].xo == DE_XO_EXP && runs[r].exp_impl == DE_EXP_JOB))
@@ -550,14 +585,16 @@ de_status de_generation(de_handle* h, int32_t n_gens, void* stream) {
     if (e) (void)hipEventRecord(e, s);
   }
   int32_t left = n_gens;
-  if (h->graph_on && !h->prof && left >= de::kHist) {
-    // whole blocks of kHist generations start on a flushed best-so-far
+  const int32_t B = h->graph_block;
+  if (B > 0 && !h->prof && left >= B) {
+    // a captured block starts on a flushed best-so-far (every call ends with
+    // one, so this runs no generation unless a caller mixes in others)
     while (left > 0 && h->pending != 0) {
       de_status st = one_generation(h, s);
       if (st != DE_OK) return st;
       --left;
     }
-    while (left >= de::kHist) {
+    while (left >= B) {
       if (!h->gexec) {
         de_status st = capture_block(h);
         if (st != DE_OK) return st;
@@ -567,9 +604,9 @@ de_status de_generation(de_handle* h, int32_t n_gens, void* stream) {
         h->base_valid = true;
       }
       HIPCHECK(h, hipGraphLaunch(h->gexec, s));
-      h->done += de::kHist;
+      h->done += static_cast<uint32_t>(B);
       h->base_value = h->done;
-      left -= de::kHist;
+      left -= B;
     }
   }
   for (int32_t k = 0; k < left; ++k) {
@@ -799,7 +836,13 @@ const char* de_last_error(const de_handle* h) {
 
 de_status de_graph(de_handle* h, int32_t enable) {
   if (!h) return fail(nullptr, DE_E_INVALID, "NULL handle");
-  h->graph_on = enable != 0;
+  if (enable < 0) return fail(h, DE_E_INVALID, "enable must be >= 0");
+  const int32_t B = enable == 1 ? de::kHist : enable;
+  if (B != h->graph_block && h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);  // captured for another block length
+    h->gexec = nullptr;
+  }
+  h->graph_block = B;
   return DE_OK;
 }
 

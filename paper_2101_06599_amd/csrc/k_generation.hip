@@ -1,6 +1,6 @@
 // The fused generation kernel: for each individual, index choice, crossover
 // mask, masked DE/rand/1 mutation, fitness and greedy selection in one pass
-// over the row (Alg 2 lines 6-14 for one row).
+// over the row (the body of Alg 2's generation loop for one row).
 //
 // Layout: TPR threads own one row (TPR >= 64, so a row is one or more whole
 // wavefronts and every per-row draw is wave-uniform).  Thread t of a row
@@ -10,198 +10,9 @@
 // into the buffer that does not hold the parent (the population is double
 // buffered per row and a flag array per generation parity says which buffer
 // holds each row), so no row is read and written in the same generation.
-#include "de_device.h"
+#include "gen_row.h"
 
 namespace de {
-
-template <typename T> struct V4 { T v[4]; };
-
-template <typename T>
-__device__ __forceinline__ V4<T> load4(const DE_GLOBAL T* p) {
-  V4<T> r;
-  if constexpr (sizeof(T) == 4) {
-    const float4 f = *(const DE_GLOBAL float4*)p;
-    r.v[0] = f.x; r.v[1] = f.y; r.v[2] = f.z; r.v[3] = f.w;
-  } else {
-    const double2 a = ((const DE_GLOBAL double2*)p)[0];
-    const double2 b = ((const DE_GLOBAL double2*)p)[1];
-    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
-  }
-  return r;
-}
-
-// Split-bf16 rotated runs: the np bf16 pieces of one chunk of (trial - o),
-// written where the product reads them (groups of 8 elements; piece p of
-// chunk c at row + ((c / 2) * np + p) * 8 + (c % 2) * 4), so no separate
-// split pass over the trial rows is needed.
-template <typename T>
-__device__ __forceinline__ void store_pieces(DE_GLOBAL __bf16* row, int np, uint32_t c,
-                                             const T (&u)[4], const V4<T>& o) {
-  if constexpr (sizeof(T) == 4) {
-    __bf16 h[4], m[4], l[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) split3(u[e] - o.v[e], h[e], m[e], l[e]);
-    DE_GLOBAL __bf16* q = row + (c >> 1) * np * 8 + (c & 1u) * 4;
-    *(DE_GLOBAL uint2*)q = make_uint2(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]));
-    *(DE_GLOBAL uint2*)(q + 8) = make_uint2(pack_bf16(m[0], m[1]), pack_bf16(m[2], m[3]));
-    if (np == 3) *(DE_GLOBAL uint2*)(q + 16) = make_uint2(pack_bf16(l[0], l[1]), pack_bf16(l[2], l[3]));
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void store4(DE_GLOBAL T* p, const T (&u)[4]) {
-  if constexpr (sizeof(T) == 4) {
-    *(DE_GLOBAL float4*)p = make_float4(u[0], u[1], u[2], u[3]);
-  } else {
-    ((DE_GLOBAL double2*)p)[0] = make_double2(u[0], u[1]);
-    ((DE_GLOBAL double2*)p)[1] = make_double2(u[2], u[3]);
-  }
-}
-
-// Everything a row needs, gathered once per row (all wave-uniform).
-template <typename T>
-struct RowCtx {
-  const DE_GLOBAL T* xi;
-  const DE_GLOBAL T* x0;
-  const DE_GLOBAL T* x1;
-  const DE_GLOBAL T* x2;
-  const DE_GLOBAL T* o;
-  DE_GLOBAL T* dst;
-  T F;
-  uint64_t thr;
-  uint32_t D, jr, L, g, i;
-  int xo;
-};
-
-// Whether chunk c holds an element of the run of L elements from j0 (mod D);
-// L = 0 is the empty run, L >= D the whole row.
-__device__ __forceinline__ bool run_touches(uint32_t j0, uint32_t L, uint32_t c, uint32_t D) {
-  if (L >= D) return true;
-  bool hit = false;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const uint32_t j = 4 * c + v;
-    const uint32_t off = j >= j0 ? j - j0 : j + D - j0;
-    hit |= j < D && off < L;
-  }
-  return hit;
-}
-
-// Chunk c of the trial row: mask bits (bit v = element 4c+v crosses) and the
-// four trial values.  Elements at or beyond D keep the parent's (padding).
-template <typename T>
-__device__ __forceinline__ uint32_t build_chunk_from(const RunDev& P, const RowCtx<T>& R,
-                                                     uint32_t c, const V4<T>& x, T (&u)[4]) {
-  const uint32_t j0 = 4 * c;
-  uint32_t m = 0;
-  if (R.xo == XO_BIN) {
-    const uint4 b = draw(P, TAG_BIN, R.g, R.i, c);
-    m = (static_cast<uint64_t>(b.x) < R.thr ? 1u : 0u) | (static_cast<uint64_t>(b.y) < R.thr ? 2u : 0u) |
-        (static_cast<uint64_t>(b.z) < R.thr ? 4u : 0u) | (static_cast<uint64_t>(b.w) < R.thr ? 8u : 0u);
-    if (R.jr >= j0 && R.jr < j0 + 4) m |= 1u << (R.jr - j0);
-  } else {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const uint32_t j = j0 + v;
-      const uint32_t off = j >= R.jr ? j - R.jr : j + R.D - R.jr;
-      m |= (off < R.L ? 1u : 0u) << v;
-    }
-  }
-  const uint32_t valid = R.D - j0 >= 4 ? 0xFu : ((1u << (R.D - j0)) - 1u);
-  m &= valid;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) u[v] = x.v[v];
-  if (m) {
-    const V4<T> a = load4(R.x0 + j0);
-    const V4<T> b = load4(R.x1 + j0);
-    const V4<T> d = load4(R.x2 + j0);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      if (m & (1u << v)) u[v] = Math<T>::fma_(R.F, b.v[v] - d.v[v], a.v[v]);
-  }
-  return m;
-}
-
-template <typename T>
-__device__ __forceinline__ uint32_t build_chunk(const RunDev& P, const RowCtx<T>& R, uint32_t c,
-                                                T (&u)[4]) {
-  return build_chunk_from(P, R, c, load4(R.xi + 4 * c), u);
-}
-
-// Trial value of a single element j (used only past the register-cached part
-// of very long rows, for the Rosenbrock neighbour of a chunk's last element).
-template <typename T>
-__device__ __forceinline__ T trial_elem(const RunDev& P, const RowCtx<T>& R, uint32_t j) {
-  bool m;
-  if (R.xo == XO_BIN) {
-    const uint4 b = draw(P, TAG_BIN, R.g, R.i, j >> 2);
-    m = static_cast<uint64_t>(word_of(b, j & 3u)) < R.thr || j == R.jr;
-  } else {
-    const uint32_t off = j >= R.jr ? j - R.jr : j + R.D - R.jr;
-    m = off < R.L;
-  }
-  return m ? Math<T>::fma_(R.F, R.x1[j] - R.x2[j], R.x0[j]) : R.xi[j];
-}
-
-// Fitness contribution of one chunk; for Rosenbrock only the pairs inside the
-// chunk (the pair that crosses into the next chunk is added separately).
-template <typename T, int FN>
-__device__ __forceinline__ T chunk_terms(const RowCtx<T>& R, uint32_t c, const T (&u)[4],
-                                         const V4<T>& o, T& zfirst) {
-  const uint32_t j0 = 4 * c;
-  T acc = T(0);
-  if constexpr (FN == FN_SPHERE || kTwoStat<FN>) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      if (j0 + v < R.D) acc += point_term<T, FN_SPHERE>(u[v], T(0));
-  } else if constexpr (FN == FN_RASTRIGIN) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      if (j0 + v < R.D) acc += point_term<T, FN>(u[v], o.v[v]);
-  } else if constexpr (FN == FN_ROSENBROCK) {
-    T z[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) z[v] = (u[v] - o.v[v]) + T(1);
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-      if (j0 + v + 1 < R.D) acc += rosen_term(z[v], z[v + 1]);
-    zfirst = z[0];
-  }
-  return acc;
-}
-
-// The second row statistic of Ackley and Griewank over one chunk.
-template <typename T, int FN>
-__device__ __forceinline__ void chunk_stat2(const RowCtx<T>& R, uint32_t c, const T (&u)[4], T& s2) {
-  if constexpr (kTwoStat<FN>) {
-    const uint32_t j0 = 4 * c;
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      if (j0 + v < R.D) s2 = stat2_join<T, FN>(s2, stat2_term<T, FN>(u[v], j0 + v));
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ T runtime_terms(int fn, const RowCtx<T>& R, uint32_t c, const T (&u)[4],
-                                           const V4<T>& o, T& zf) {
-  if (fn == FN_SPHERE) return chunk_terms<T, FN_SPHERE>(R, c, u, o, zf);
-  if (fn == FN_RASTRIGIN) return chunk_terms<T, FN_RASTRIGIN>(R, c, u, o, zf);
-  return chunk_terms<T, FN_ROSENBROCK>(R, c, u, o, zf);
-}
-
-template <int TPR> struct Shape {
-  static constexpr int BS = TPR >= 256 ? TPR : 256;  // threads per block
-  static constexpr int RPB = BS / TPR;               // rows per block
-  static constexpr int NW = TPR / 64;                // wavefronts per row
-  // chunks of 4 elements held in registers per thread: D <= 16 * TPR (20 * 512
-  // for 512-wide rows, 8 * 128 for 128-wide rows) stays in registers between
-  // evaluation and write-back
-  static constexpr int MAXIT = TPR == 512 ? 5 : TPR == 128 ? 2 : 4;
-  // 64- and 128-lane rows issue every cached chunk's parent loads before
-  // using any (more loads in flight per wave); wider rows would lose
-  // occupancy to it
-  static constexpr bool PREFETCH = TPR <= 128;
-};
 
 // FN: a fixed function, FN_ANY (taken from the run record) or FN_NONE (build
 // and store the trial only; the rotated function's product evaluates it).
@@ -215,7 +26,6 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   __shared__ T red[S::RPB * S::NW];
   __shared__ uint32_t redc[S::RPB * S::NW];
   __shared__ T red2[kTwoStat<FN> ? S::RPB * S::NW : 1];
-  __shared__ T zsh[(FN == FN_ROSENBROCK || FN == FN_ANY) ? S::RPB * TPR * MAXIT + 1 : 1];
 
   const uint32_t t = threadIdx.x % TPR;
   const uint32_t slot = threadIdx.x / TPR;
@@ -246,7 +56,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   DE_GLOBAL T* fit = gmut<T>(P.fit);
   // i is the row's position in Alg 2 (it addresses every draw); si is the
   // storage row of the individual at that position (i itself unless the run
-  // shuffles, Alg 2 line 5).
+  // shuffles, Alg 2).
   const uint32_t si = __builtin_amdgcn_readfirstlane(row_of(P, R.g, i));
   const T fold = FN != FN_NONE ? fit[si] : T(0);  // only row si's block writes it
   // The row's dirty record (only row si's block writes it): lane l holds its
@@ -254,7 +64,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   // write-back (a scalar load would hold up every later scalar-cache wait).
   const uint32_t dword = gconst<uint32_t>(P.dirty)[4 * static_cast<int64_t>(si) + (__lane_id() & 3u)];
 
-  // Alg 2 line 6 and the index draws of Alg 6: base r0, difference r1 - r2,
+  // Alg 2's index choice and the draws of Alg 6: base r0, difference r1 - r2,
   // then the storage rows they name.
   uint32_t r0, r1, r2;
   pick_scheme(P, R.g, i, N, r0, r1, r2);
@@ -273,7 +83,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   // parent row is requested as soon as its flag is back, and the run length
   // is counted while that row is in flight.
   const uint32_t fi = cur[si], f0 = cur[r0], f1 = cur[r1], f2 = cur[r2];
-  // Alg 2 line 7: the crossover mask comes first (j_rand, and L for exp/NEC).
+  // Alg 2 builds the crossover mask first (j_rand, and L for exp/NEC).
   const uint4 bx = draw(P, TAG_XO, R.g, i, 0);
   R.jr = __builtin_amdgcn_readfirstlane(scale_index(bx.x, R.D));
   uint64_t t1 = 0;
@@ -296,9 +106,8 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   T acc = T(0);
   T acc2 = stat2_init<T, FN>();  // Ackley / Griewank only
   uint32_t cnt = 0;
-  T* zrow = zsh + slot * (TPR * MAXIT);
 
-  // Alg 2 lines 8-10 for this row: trial = parent with the masked elements
+  // Alg 2's copy, masked mutation and evaluation for this row: trial = parent with the masked elements
   // replaced by x_r0 + F (x_r1 - x_r2), evaluated on the fly.
   // Phase 1 (64- and 128-lane rows of one run): every cached chunk's parent (and
   // shift) loads go out together; wide rows and batched launches, where
@@ -308,8 +117,8 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   // Rotated split-bf16 runs (FP32 only) also write the pieces of trial - o.
   const bool pieces = FN == FN_NONE && sizeof(T) == 4 && P.apc != nullptr;
   const int np = P.mm == MM_BF16X6 ? 3 : 2;
-  DE_GLOBAL __bf16* prow = pieces ? gmut<__bf16>(P.apc) + static_cast<int64_t>(si) * np * P.ldk
-                                  : nullptr;
+  DE_GLOBAL __bf16* prow = pieces ? gmut<__bf16>(P.apc) + static_cast<int64_t>(si) * P.ldk : nullptr;
+  const int64_t plane = P.N * P.ldk;  // pitch of the piece planes
   const bool shifted = (kShift && (FN != FN_ANY || fn != FN_SPHERE)) || pieces;
   V4<T> xs[MAXIT], os[MAXIT];
   if constexpr (kPrefetch) {
@@ -328,11 +137,18 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
                                                           : exp_length_serial(P, R.g, i);
   R.L = __builtin_amdgcn_readfirstlane(R.L);
   // Phase 2: mask, donors where the mask is set, trial and fitness terms.
+  // Rosenbrock's pair across chunks c and c + 1 is added right after chunk c:
+  // the first z of chunk c + 1 is the next lane's (a wavefront's chunks are
+  // consecutive) or, for a wavefront's last lane, computed from the element.
+  // Whether the row is Rosenbrock is wave-uniform (one run per wavefront).
+  const bool rosen = FN == FN_ROSENBROCK || (FN == FN_ANY && fn == FN_ROSENBROCK);
 #pragma unroll
   for (int k = 0; k < MAXIT; ++k) {
     const uint32_t c = k * TPR + t;
+    const bool in = c < nchunk;
     mb[k] = 0;
-    if (c < nchunk) {
+    T zf = T(0);
+    if (in) {
       if constexpr (!kPrefetch) {
         xs[k] = load4(R.xi + 4 * c);
         if (shifted) os[k] = load4(R.o + 4 * c);
@@ -340,49 +156,46 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
       mb[k] = build_chunk_from(P, R, c, xs[k], u[k]);
       cnt += __popc(mb[k]);
       if constexpr (FN != FN_NONE) {
-        T zf = T(0);
         acc += FN == FN_ANY ? runtime_terms(fn, R, c, u[k], os[k], zf)
                             : chunk_terms<T, FN>(R, c, u[k], os[k], zf);
         chunk_stat2<T, FN>(R, c, u[k], acc2);
-        if constexpr (FN == FN_ROSENBROCK || FN == FN_ANY) zrow[c] = zf;
+      }
+    }
+    if constexpr (FN == FN_ROSENBROCK || FN == FN_ANY) {
+      if (rosen) {
+        const T znb = __shfl_down(zf, 1);
+        if (in && 4 * c + 4 < R.D) {
+          const T zn = lane != 63 ? znb : (trial_elem(P, R, 4 * c + 4) - R.o[4 * c + 4]) + T(1);
+          const T zl = (u[k][3] - os[k].v[3]) + T(1);
+          acc += rosen_term(zl, zn);
+        }
       }
     }
   }
-  // Rows longer than the register cache: evaluate the rest now, rebuild later.
-  for (uint32_t c = MAXIT * TPR + t; c < nchunk; c += TPR) {
-    T v[4];
-    const uint32_t m = build_chunk(P, R, c, v);
-    cnt += __popc(m);
-    if constexpr (FN != FN_NONE) {
-      T zf = T(0);
-      V4<T> ov;
-      if (kShift && (FN != FN_ANY || fn != FN_SPHERE)) ov = load4(R.o + 4 * c);
-      acc += FN == FN_ANY ? runtime_terms(fn, R, c, v, ov, zf)
-                          : chunk_terms<T, FN>(R, c, v, ov, zf);
-      chunk_stat2<T, FN>(R, c, v, acc2);
-      if ((FN == FN_ROSENBROCK || (FN == FN_ANY && fn == FN_ROSENBROCK)) && 4 * c + 4 < R.D) {
-        const T zn = (trial_elem(P, R, 4 * c + 4) - R.o[4 * c + 4]) + T(1);
-        const T zl = (v[3] - R.o[4 * c + 3]) + T(1);
-        acc += rosen_term(zl, zn);
+  // Rows longer than the register cache: evaluate the rest now, rebuild later
+  // (the same trip count for every lane of the row, for the shuffle).
+  for (uint32_t cb = MAXIT * TPR; cb < nchunk; cb += TPR) {
+    const uint32_t c = cb + t;
+    const bool in = c < nchunk;
+    T v[4] = {T(0), T(0), T(0), T(0)};
+    T zf = T(0);
+    V4<T> ov;
+    if (in) {
+      const uint32_t m = build_chunk(P, R, c, v);
+      cnt += __popc(m);
+      if constexpr (FN != FN_NONE) {
+        if (kShift && (FN != FN_ANY || fn != FN_SPHERE)) ov = load4(R.o + 4 * c);
+        acc += FN == FN_ANY ? runtime_terms(fn, R, c, v, ov, zf)
+                            : chunk_terms<T, FN>(R, c, v, ov, zf);
+        chunk_stat2<T, FN>(R, c, v, acc2);
       }
     }
-  }
-
-  if constexpr (FN == FN_ROSENBROCK || FN == FN_ANY) {
-    __syncthreads();  // unconditional: rows of one block may run different functions
-    if (FN == FN_ROSENBROCK || fn == FN_ROSENBROCK) {
-#pragma unroll
-      for (int k = 0; k < MAXIT; ++k) {
-        const uint32_t c = k * TPR + t;
-        if (c < nchunk && 4 * c + 4 < R.D) {
-          const uint32_t cn = c + 1;
-          T zn;
-          if (cn < MAXIT * TPR) {
-            zn = zrow[cn];
-          } else {
-            zn = (trial_elem(P, R, 4 * cn) - R.o[4 * cn]) + T(1);
-          }
-          const T zl = (u[k][3] - R.o[4 * c + 3]) + T(1);
+    if constexpr (FN == FN_ROSENBROCK || FN == FN_ANY) {
+      if (rosen) {
+        const T znb = __shfl_down(zf, 1);
+        if (in && 4 * c + 4 < R.D) {
+          const T zn = lane != 63 ? znb : (trial_elem(P, R, 4 * c + 4) - R.o[4 * c + 4]) + T(1);
+          const T zl = (v[3] - ov.v[3]) + T(1);
           acc += rosen_term(zl, zn);
         }
       }
@@ -418,7 +231,7 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   const T fu = canon(fraw);
   bool win = true;
   if constexpr (FN != FN_NONE) {
-    // Alg 1 line 10 / Alg 2 line 11: strictly lower fitness replaces.
+    // Alg 1's replacement test, as in Alg 2's selection: strictly lower fitness replaces.
     win = fu < fold;
   }
   if (win) {
@@ -438,27 +251,27 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
         const uint32_t c = k * TPR + t;
         if (c < nchunk) {
           store4(R.dst + 4 * c, u[k]);
-          if (pieces) store_pieces(prow, np, c, u[k], os[k]);
+          if (pieces) store_pieces(prow, plane, np, c, u[k], os[k]);
         }
       }
       for (uint32_t c = MAXIT * TPR + t; c < nchunk; c += TPR) {
         T v[4];
         build_chunk(P, R, c, v);
         store4(R.dst + 4 * c, v);
-        if (pieces) store_pieces(prow, np, c, v, load4(R.o + 4 * c));
+        if (pieces) store_pieces(prow, plane, np, c, v, load4(R.o + 4 * c));
       }
     } else {
 #pragma unroll
       for (int k = 0; k < MAXIT; ++k) {
         const uint32_t c = k * TPR + t;
         if (c < nchunk && (mb[k] != 0 || run_touches(pj, pl, c, R.D))) store4(R.dst + 4 * c, u[k]);
-        if (pieces && c < nchunk) store_pieces(prow, np, c, u[k], os[k]);
+        if (pieces && c < nchunk) store_pieces(prow, plane, np, c, u[k], os[k]);
       }
       for (uint32_t c = MAXIT * TPR + t; c < nchunk; c += TPR) {
         T v[4];
         const uint32_t m = build_chunk(P, R, c, v);
         if (m != 0 || run_touches(pj, pl, c, R.D)) store4(R.dst + 4 * c, v);
-        if (pieces) store_pieces(prow, np, c, v, load4(R.o + 4 * c));
+        if (pieces) store_pieces(prow, plane, np, c, v, load4(R.o + 4 * c));
       }
     }
     if (t == 0 && pw != 0)
@@ -537,8 +350,12 @@ static hipError_t go_xo(const GenLaunch& L, int xo, bool batched) {
 template <typename T>
 static hipError_t go_fn(const GenLaunch& L, int fn, int xo, bool batched) {
   if (batched) {
-    if (L.tpr != 64) return hipErrorInvalidValue;
-    return go<T, FN_ANY, XO_ANY, 64>(L, true);
+    switch (L.tpr) {
+      case 64: return go<T, FN_ANY, XO_ANY, 64>(L, true);
+      case 128: return go<T, FN_ANY, XO_ANY, 128>(L, true);
+      case 256: return go<T, FN_ANY, XO_ANY, 256>(L, true);
+      default: return hipErrorInvalidValue;
+    }
   }
   switch (fn) {
     case FN_SPHERE: return go_xo<T, FN_SPHERE>(L, xo, false);

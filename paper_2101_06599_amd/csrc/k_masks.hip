@@ -6,6 +6,38 @@
 
 namespace de {
 
+// Mask bits of chunk c (elements 4c .. 4c+3; bit v for element 4c + v).
+template <int XO>
+__device__ __forceinline__ uint32_t chunk_mask(const RunDev& P, uint32_t g, uint32_t i, uint32_t c,
+                                               uint32_t jr, uint32_t L, uint32_t D) {
+  const uint32_t j0 = 4 * c;
+  uint32_t m = 0;
+  if constexpr (XO == XO_BIN) {
+    const uint4 b = draw(P, TAG_BIN, g, i, c);
+    m = (static_cast<uint64_t>(b.x) < P.thr ? 1u : 0u) | (static_cast<uint64_t>(b.y) < P.thr ? 2u : 0u) |
+        (static_cast<uint64_t>(b.z) < P.thr ? 4u : 0u) | (static_cast<uint64_t>(b.w) < P.thr ? 8u : 0u);
+    if (jr >= j0 && jr < j0 + 4) m |= 1u << (jr - j0);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t j = j0 + v;
+      const uint32_t off = j >= jr ? j - jr : j + D - jr;
+      m |= (off < L ? 1u : 0u) << v;
+    }
+  }
+  return m;
+}
+
+// Four mask bits as four 0/1 bytes of a little-endian word.
+__device__ __forceinline__ uint32_t mask_bytes(uint32_t m) {
+  return (m & 1u) | ((m & 2u) << 7) | ((m & 4u) << 14) | ((m & 8u) << 21);
+}
+
+// One wavefront per individual.  When D is a multiple of 4, every 16-byte
+// aligned unit of a row starts at a chunk boundary: a lane builds four chunks
+// and writes them with one 16-byte store, and the at most three chunks before
+// the row's first and after its last aligned unit take 4-byte stores.  Other
+// rows are written four bytes (or, unaligned, one byte) at a time.
 template <int XO>
 __global__ void __launch_bounds__(256) k_masks(const RunDev* __restrict__ runs, int32_t run,
                                                uint32_t g, uint8_t* __restrict__ out) {
@@ -23,28 +55,33 @@ __global__ void __launch_bounds__(256) k_masks(const RunDev* __restrict__ runs, 
     L = P.exp_impl == EXPI_SCAN ? exp_length_scan(P, g, i) : exp_length_serial(P, g, i);
   const int64_t base = static_cast<int64_t>(i) * D;
   DE_GLOBAL uint8_t* o = gmut<uint8_t>(out) + base;
-  const bool word_aligned = (base & 3) == 0;
-  for (uint32_t c = lane; 4 * c < D; c += 64) {
-    const uint32_t j0 = 4 * c;
-    uint32_t m = 0;
-    if constexpr (XO == XO_BIN) {
-      const uint4 b = draw(P, TAG_BIN, g, i, c);
-      m = (static_cast<uint64_t>(b.x) < P.thr ? 1u : 0u) |
-          (static_cast<uint64_t>(b.y) < P.thr ? 2u : 0u) |
-          (static_cast<uint64_t>(b.z) < P.thr ? 4u : 0u) |
-          (static_cast<uint64_t>(b.w) < P.thr ? 8u : 0u);
-      if (jr >= j0 && jr < j0 + 4) m |= 1u << (jr - j0);
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const uint32_t j = j0 + v;
-        const uint32_t off = j >= jr ? j - jr : j + D - jr;
-        m |= (off < L ? 1u : 0u) << v;
-      }
+  const uint32_t nchunk = (D + 3) >> 2;
+  if ((D & 3u) == 0) {
+    // chunks [0, h) before the first 16-byte boundary, [h, h + 4 nu) in
+    // 16-byte units, the rest after the last one
+    const uint32_t h = min(static_cast<uint32_t>((16 - (base & 15)) & 15) >> 2, nchunk);
+    const uint32_t nu = (nchunk - h) >> 2;
+    for (uint32_t u = lane; u < nu; u += 64) {
+      const uint32_t c = h + 4 * u;
+      uint4 v;
+      v.x = mask_bytes(chunk_mask<XO>(P, g, i, c, jr, L, D));
+      v.y = mask_bytes(chunk_mask<XO>(P, g, i, c + 1, jr, L, D));
+      v.z = mask_bytes(chunk_mask<XO>(P, g, i, c + 2, jr, L, D));
+      v.w = mask_bytes(chunk_mask<XO>(P, g, i, c + 3, jr, L, D));
+      *(DE_GLOBAL uint4*)(o + 4 * c) = v;
     }
-    const uint32_t bytes = (m & 1u) | ((m & 2u) << 7) | ((m & 4u) << 14) | ((m & 8u) << 21);
+    const uint32_t tail = h + 4 * nu;
+    if (lane < h) *(DE_GLOBAL uint32_t*)(o + 4 * lane) = mask_bytes(chunk_mask<XO>(P, g, i, lane, jr, L, D));
+    if (tail + lane < nchunk)
+      *(DE_GLOBAL uint32_t*)(o + 4 * (tail + lane)) = mask_bytes(chunk_mask<XO>(P, g, i, tail + lane, jr, L, D));
+    return;
+  }
+  const bool word_aligned = (base & 3) == 0;
+  for (uint32_t c = lane; c < nchunk; c += 64) {
+    const uint32_t j0 = 4 * c;
+    const uint32_t m = chunk_mask<XO>(P, g, i, c, jr, L, D);
     if (word_aligned && j0 + 4 <= D) {
-      *(DE_GLOBAL uint32_t*)(o + j0) = bytes;
+      *(DE_GLOBAL uint32_t*)(o + j0) = mask_bytes(m);
     } else {
 #pragma unroll
       for (int v = 0; v < 4; ++v)

@@ -5,7 +5,7 @@
 
 namespace de {
 
-// ---- initialisation (Alg 2 lines 2-3) -------------------------------------
+// ---- initialisation (Alg 2, before its generation loop) --------------------
 
 // Uniform in [lo, hi]: FP64 takes 53 bits from two words of block j/2, FP32
 // takes 24 bits from word j%4 of block j/4.
@@ -116,7 +116,7 @@ __device__ T block_row_fitness_rt(int fn, const T* x, const T* o, uint32_t D) {
   return block_row_fitness<T, FN_ROSENBROCK>(x, o, D);
 }
 
-// Initial evaluation (Alg 2 line 3): rows of buffer 0.
+// Initial evaluation (Alg 2, before its generation loop): rows of buffer 0.
 template <typename T>
 __global__ void __launch_bounds__(256) k_eval_pop(const RunDev* __restrict__ runs, int32_t run) {
   const RunDev& P = runs[run];
@@ -164,9 +164,9 @@ __global__ void __launch_bounds__(256) k_eval_select(const RunDev* __restrict__ 
 }
 
 // ---- classic exponential crossover, one job per individual (Alg 8) --------
-// One work-item builds individual i's whole trial: copy the parent (line 3),
+// One work-item builds individual i's whole trial: copy the parent,
 // then walk from j_rand taking the mutant element and drawing the next
-// uniform until a draw reaches Cr or the whole row is taken (lines 4-9).
+// uniform until a draw reaches Cr or the whole row is taken.
 template <typename T>
 __global__ void __launch_bounds__(64) k_pexp_trial(const RunDev* __restrict__ runs, int32_t run,
                                                    GenNo gn) {
@@ -348,17 +348,7 @@ __global__ void __launch_bounds__(256) k_best_fp64(const RunDev* __restrict__ ru
     return;
   }
   double acc = 0.0;
-  if (P.fn == FN_ELLIPSOID) {
-    // z_k = sum_j M_kj (x_j - o_j) with the caller's FP64 M
-    for (uint32_t k = threadIdx.x; k < D; k += blockDim.x) {
-      double z = 0.0;
-      for (uint32_t j = 0; j < D; ++j)
-        z = __builtin_fma(P.rot[static_cast<int64_t>(k) * D + j],
-                          static_cast<double>(x[j]) - static_cast<double>(o[j]), z);
-      const double wk = static_cast<double>(static_cast<const T*>(P.w)[k]);
-      acc = __builtin_fma(wk * z, z, acc);
-    }
-  } else {
+  {
     for (uint32_t j = threadIdx.x; j < D; j += blockDim.x) {
       const double xj = static_cast<double>(x[j]);
       const double oj = P.fn == FN_SPHERE ? 0.0 : static_cast<double>(o[j]);
@@ -373,6 +363,49 @@ __global__ void __launch_bounds__(256) k_best_fp64(const RunDev* __restrict__ ru
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) *out = canon(red[0] + red[1] + red[2] + red[3]);
+}
+
+// The rotated function's FP64 recompute: term k = w_k z_k^2 with
+// z_k = sum_j M_kj (x_j - o_j), the caller's FP64 M and the weights
+// 10^(6k/(D-1)) in FP64; one wavefront per k reads row k of M in coalesced
+// runs and reduces its lanes in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_best_rot_terms(const RunDev* __restrict__ runs,
+                                                        int32_t run, uint32_t gcur) {
+  const RunDev& P = runs[run];
+  const uint32_t N = static_cast<uint32_t>(P.N), D = static_cast<uint32_t>(P.D);
+  const uint32_t k = blockIdx.x * 4 + threadIdx.x / 64;
+  if (k >= D) return;  // whole wavefronts leave together
+  const int64_t i = P.best->idx;
+  const uint8_t* cur = P.flags + (run_gen(P, gcur) & 1u) * static_cast<int64_t>(N);
+  const T* x = static_cast<const T*>(P.X[cur[i]]) + i * P.ld;
+  const T* o = static_cast<const T*>(P.o);
+  const double* m = P.rot + static_cast<int64_t>(k) * D;
+  double z = 0.0;
+  for (uint32_t j = threadIdx.x % 64; j < D; j += 64)
+    z = __builtin_fma(m[j], static_cast<double>(x[j]) - static_cast<double>(o[j]), z);
+  z = wave_sum(z);
+  if (threadIdx.x % 64 == 0) {
+    const double wk = D > 1 ? pow(10.0, 6.0 * static_cast<double>(k) / static_cast<double>(D - 1)) : 1.0;
+    P.bpart[k] = wk * z * z;
+  }
+}
+
+// Sum of the D terms in a fixed order (strided per thread, then a tree).
+__global__ void __launch_bounds__(256) k_best_rot_sum(const RunDev* __restrict__ runs, int32_t run,
+                                                      double* __restrict__ out) {
+  const RunDev& P = runs[run];
+  const int64_t D = P.D;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < D; k += 256) acc += P.bpart[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = canon(red[0]);
 }
 
 // ---- state helpers ---------------------------------------------------------
@@ -484,6 +517,15 @@ hipError_t launch_best_flush(const RunDev* runs, int n_runs, GenNo gfirst, int c
 
 hipError_t launch_best_fp64(const RunDev* runs, const RunDev& h, int run, uint32_t gcur,
                             double* out, hipStream_t s) {
+  if (h.fn == FN_ELLIPSOID) {
+    const unsigned blocks = static_cast<unsigned>((h.D + 3) / 4);
+    if (h.dtype == 0)
+      hipLaunchKernelGGL(k_best_rot_terms<double>, dim3(blocks), dim3(256), 0, s, runs, run, gcur);
+    else
+      hipLaunchKernelGGL(k_best_rot_terms<float>, dim3(blocks), dim3(256), 0, s, runs, run, gcur);
+    hipLaunchKernelGGL(k_best_rot_sum, dim3(1), dim3(256), 0, s, runs, run, out);
+    return hipGetLastError();
+  }
   if (h.dtype == 0) hipLaunchKernelGGL(k_best_fp64<double>, dim3(1), dim3(256), 0, s, runs, run, gcur, out);
   else hipLaunchKernelGGL(k_best_fp64<float>, dim3(1), dim3(256), 0, s, runs, run, gcur, out);
   return hipGetLastError();

@@ -2,25 +2,26 @@
 // the one dense contraction of the path, Z = (U - 1 o^T) M^T, an N x D x D
 // product with both operands contiguous along the contraction index.
 //
-// One kernel does the product on the matrix cores with the shift subtraction
-// fused into the A-tile load (FP32/FP64) and the weighted square sum fused
-// into the epilogue, so Z is never stored: each block writes one partial sum
-// per row for its 128 output columns.  A second kernel adds the partials of a
-// row in a fixed order and performs greedy selection.  For the split-bf16
-// modes a pass before the product writes the hi/mid/lo pieces of U - o once
-// (the product reads every A row once per column tile, 16 times at D = 2048,
-// and splitting inside it cost matrix-core time).
+// One kernel does the product on the matrix cores with the weighted square
+// sum fused into the epilogue, so Z is never stored: each block writes one
+// partial sum per row for its 128 output columns.  A second kernel adds the
+// partials of a row in a fixed order and performs greedy selection.
 //
-// Modes: FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_16x16x4), and bf16
-// splits of both operands into 2 or 3 pieces whose 3 or 6 leading cross
-// products are accumulated in FP32 (v_mfma_f32_16x16x32_bf16).
+// Modes: FP64 (v_mfma_f64_16x16x4) and FP32 (v_mfma_f32_16x16x4), with the
+// shift subtracted in the A-tile load; and splits of both operands into 2 or
+// 3 bf16 pieces whose 3 or 6 leading cross products are accumulated in FP32
+// (v_mfma_f32_16x16x32_bf16 / v_mfma_f32_32x32x16_bf16).  The bf16 pieces of
+// U - o are written by the trial kernel (or a split pass for rows no trial
+// kernel wrote), those of M once at set-up.
 //
-// Lane layout of the 16x16 MFMA tiles used here (KPL = k values per lane:
-// 8 for bf16, 1 for f32/f64): lane l supplies A[l%16][(l/16)*KPL + e] and
-// B[(l/16)*KPL + e][l%16].  Accumulator register r of lane l holds
-// C[(l/16)*4 + r][l%16] for the f32/bf16 forms and C[4r + l/16][l%16] for
-// the f64 form (checked on gfx950 with integer-valued operands).
+// Lane layouts (checked on gfx950 with integer-valued operands): in the 16x16
+// forms lane l supplies A[l%16][(l/16)*KPL + e] and B[(l/16)*KPL + e][l%16]
+// (KPL = 8 for bf16, 1 for f32/f64); accumulator register r of lane l holds
+// C[(l/16)*4 + r][l%16] for the f32/bf16 forms and C[4r + l/16][l%16] for the
+// f64 form.  In the 32x32x16 form lane l supplies A[l%32][(l/32)*8 + e] and
+// B[(l/32)*8 + e][l%32], and register r holds C[8(r/4) + 4(l/32) + r%4][l%32].
 #include <type_traits>
+#include <utility>
 
 #include "de_device.h"
 
@@ -29,6 +30,7 @@ namespace de {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(4))) double f64x4;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 
 template <int MODE> struct MM;
@@ -38,14 +40,8 @@ template <> struct MM<MM_FP64> {
 template <> struct MM<MM_FP32> {
   using T = float; using L = float; static constexpr int P = 1, KT = 32, BM = 128, BN = 128, PAD = 4;
 };
-template <> struct MM<MM_BF16X3> {
-  using T = float; using L = __bf16; static constexpr int P = 2, KT = 32, BM = 128, BN = 128, PAD = 8;
-};
-template <> struct MM<MM_BF16X6> {
-  using T = float; using L = __bf16; static constexpr int P = 3, KT = 32, BM = 128, BN = 128, PAD = 8;
-};
 
-int rot_tile_n() { return 128; }  // BN of the FP32/bf16 modes; FP64 uses 64 (2 partials per 128)
+int rot_tile_n() { return 128; }  // BN of the FP32 and bf16 modes; FP64 uses 64
 
 // Row source for the A operand.
 //   src 0: trials of the coming generation (non-current buffer of each row)
@@ -73,10 +69,8 @@ __device__ __forceinline__ void copy16(V* __restrict__ dst, const V* __restrict_
     reinterpret_cast<uint4*>(dst)[q] = reinterpret_cast<const uint4*>(src)[q];
 }
 
-// Pieces of A = U - o for the split-bf16 modes, zero past D, interleaved by
-// groups of 8 k: the P pieces of group g of row i are 8 consecutive values
-// each at apc + ((i * ldk / 8 + g) * P + p) * 8, so a thread of the product
-// reads its segment's pieces in one contiguous run.  One thread per group.
+// Pieces of A = U - o for the split-bf16 modes, zero past D: piece p of row i
+// is row i of plane p, apc + (p N + i) ldk.  One thread per 8 values.
 template <int P>
 __global__ void __launch_bounds__(256) k_rot_split(const RunDev* __restrict__ runs, int32_t run,
                                                   int src, GenNo ghn, int64_t rows) {
@@ -101,31 +95,28 @@ __global__ void __launch_bounds__(256) k_rot_split(const RunDev* __restrict__ ru
     m[v] = pack_bf16(m0, m1);
     l[v] = pack_bf16(l0, l1);
   }
-  uint4* out = reinterpret_cast<uint4*>(static_cast<__bf16*>(Pr.apc) + (i * (ldk / 8) + k0 / 8) * P * 8);
-  out[0] = make_uint4(h[0], h[1], h[2], h[3]);
-  out[1] = make_uint4(m[0], m[1], m[2], m[3]);
-  if constexpr (P == 3) out[2] = make_uint4(l[0], l[1], l[2], l[3]);
+  __bf16* out = static_cast<__bf16*>(Pr.apc) + i * ldk + k0;
+  const int64_t plane = Pr.N * ldk;
+  *reinterpret_cast<uint4*>(out) = make_uint4(h[0], h[1], h[2], h[3]);
+  *reinterpret_cast<uint4*>(out + plane) = make_uint4(m[0], m[1], m[2], m[3]);
+  if constexpr (P == 3) *reinterpret_cast<uint4*>(out + 2 * plane) = make_uint4(l[0], l[1], l[2], l[3]);
 }
 
-// The product for one 128x128 (FP64: 64x64) tile of Z.  The next K slice is
+// FP32 / FP64 product, one 128x128 (FP64: 64x64) tile of Z per block, with
+// the shift subtracted as the A slice goes into LDS.  The next K slice is
 // fetched into registers while the matrix cores work on the current one from
-// LDS; the slice is then split (bf16 modes) and written into the other LDS
-// buffer, so one barrier per K step separates the two.
+// LDS, then written into the other LDS buffer, so one barrier per K step
+// separates the two.
 template <int MODE>
 __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ runs, int32_t run,
                                                  int src, GenNo ghn, int64_t rows) {
   const uint32_t gh = gen_value(ghn);
   using C = MM<MODE>;
   using T = typename C::T;
-  using LT = typename C::L;
-  constexpr int BM = C::BM, BN = C::BN, KT = C::KT, P = C::P, LDK = KT + C::PAD;
+  constexpr int BM = C::BM, BN = C::BN, KT = C::KT, LDK = KT + C::PAD;
   constexpr int WM = BM / 32, WN = BN / 32;  // 16x16 subtiles per wave (2x2 waves)
-  // FP32/FP64 slices are small: two LDS buffers, one barrier per K step.  The
-  // split-bf16 slices are 2-3x larger: one buffer (two barriers per step) so
-  // that two blocks fit on a CU.
-  constexpr int NBUF = P == 1 ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) LT As[NBUF][P][BM][LDK];
-  __shared__ __attribute__((aligned(16))) LT Bs[NBUF][P][BN][LDK];
+  __shared__ __attribute__((aligned(16))) T As[2][BM][LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BN][LDK];
   __shared__ T red[2][BM];
 
   const RunDev& Pr = runs[run];
@@ -150,65 +141,44 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   const int a_r = tid / A_TPR, a_k = (tid % A_TPR) * A_SEG;
   const int b_r = tid / B_TPR, b_k = (tid % B_TPR) * B_SEG;
   const int64_t ai = min(row0 + a_r, rows - 1);
-  // FP32/FP64: the row itself and the shift; bf16 modes: the row's pieces
-  const T* arow = P == 1 ? a_row<T>(Pr, src, gh, ai) + a_k : nullptr;
+  const T* arow = a_row<T>(Pr, src, gh, ai) + a_k;
   const T* orow = static_cast<const T*>(Pr.o) + a_k;
-  const __bf16* aprow = P == 1 ? nullptr
-                               : static_cast<const __bf16*>(Pr.apc) + (ai * (ldk / 8) + a_k / 8) * P * 8;
-  const LT* brow[P];
-#pragma unroll
-  for (int p = 0; p < P; ++p)  // rows of M pieces are padded to a multiple of 128
-    brow[p] = static_cast<const LT*>(Pr.B[p]) + (col0 + b_r) * ldk + b_k;
+  // rows of M are padded to a multiple of 256
+  const T* brow = static_cast<const T*>(Pr.B[0]) + (col0 + b_r) * ldk + b_k;
 
   // The next K slice, held as 16-byte vectors only (element access through
   // casts of local arrays would put them in scratch memory).
-  constexpr int AV = (P == 1 ? A_SEG * static_cast<int>(sizeof(T)) : A_SEG * 2) / 16;
-  constexpr int BV = B_SEG * static_cast<int>(sizeof(LT)) / 16;
-  constexpr int AE = 16 / static_cast<int>(sizeof(T));   // A elements per vector (P == 1)
-  constexpr int BE = 16 / static_cast<int>(sizeof(LT));  // B elements per vector
-  static_assert(AV * (P == 1 ? AE : 8) == A_SEG && BV * BE == B_SEG, "whole 16-byte segments");
-  uint4 va[P][AV], vo[P == 1 ? AV : 1], vb[P][BV];
+  constexpr int E = 16 / static_cast<int>(sizeof(T));  // elements per vector
+  constexpr int AV = A_SEG / E, BV = B_SEG / E;
+  static_assert(AV * E == A_SEG && BV * E == B_SEG, "whole 16-byte segments");
+  uint4 va[AV], vo[AV], vb[BV];
   auto ld16 = [](const void* p) { return *reinterpret_cast<const uint4*>(p); };
   auto st16 = [](void* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; };
 #define DE_ROT_FETCH(K0)                                                                  \
   do {                                                                                    \
     const int64_t k0_ = (K0);                                                             \
-    if constexpr (P == 1) {                                                               \
-      _Pragma("unroll") for (int q = 0; q < AV; ++q) {                                   \
-        va[0][q] = ld16(arow + k0_ + q * AE);                                             \
-        vo[q] = ld16(orow + k0_ + q * AE); /* padding columns are zero on both sides */   \
-      }                                                                                   \
-    } else {                                                                              \
-      _Pragma("unroll") for (int g = 0; g < AV; ++g)                                     \
-        _Pragma("unroll") for (int p = 0; p < P; ++p)                                    \
-          va[p][g] = ld16(aprow + (k0_ / 8 + g) * P * 8 + p * 8);                         \
+    _Pragma("unroll") for (int q = 0; q < AV; ++q) {                                     \
+      va[q] = ld16(arow + k0_ + q * E);                                                   \
+      vo[q] = ld16(orow + k0_ + q * E); /* padding columns are zero on both sides */      \
     }                                                                                     \
-    _Pragma("unroll") for (int p = 0; p < P; ++p)                                        \
-      _Pragma("unroll") for (int q = 0; q < BV; ++q) vb[p][q] = ld16(brow[p] + k0_ + q * BE); \
+    _Pragma("unroll") for (int q = 0; q < BV; ++q) vb[q] = ld16(brow + k0_ + q * E);     \
   } while (0)
 #define DE_ROT_STASH(BUF)                                                                 \
   do {                                                                                    \
     const int b_ = (BUF);                                                                 \
-    if constexpr (P == 1) {                                                               \
-      _Pragma("unroll") for (int q = 0; q < AV; ++q) {                                   \
-        if constexpr (sizeof(T) == 4) {                                                   \
-          const float4 x = __builtin_bit_cast(float4, va[0][q]);                         \
-          const float4 y = __builtin_bit_cast(float4, vo[q]);                            \
-          st16(&As[b_][0][a_r][a_k + q * AE],                                             \
-               __builtin_bit_cast(uint4, make_float4(x.x - y.x, x.y - y.y, x.z - y.z, x.w - y.w))); \
-        } else {                                                                          \
-          const double2 x = __builtin_bit_cast(double2, va[0][q]);                       \
-          const double2 y = __builtin_bit_cast(double2, vo[q]);                          \
-          st16(&As[b_][0][a_r][a_k + q * AE],                                             \
-               __builtin_bit_cast(uint4, make_double2(x.x - y.x, x.y - y.y)));           \
-        }                                                                                 \
+    _Pragma("unroll") for (int q = 0; q < AV; ++q) {                                     \
+      if constexpr (sizeof(T) == 4) {                                                     \
+        const float4 x = __builtin_bit_cast(float4, va[q]);                              \
+        const float4 y = __builtin_bit_cast(float4, vo[q]);                              \
+        st16(&As[b_][a_r][a_k + q * E],                                                   \
+             __builtin_bit_cast(uint4, make_float4(x.x - y.x, x.y - y.y, x.z - y.z, x.w - y.w))); \
+      } else {                                                                            \
+        const double2 x = __builtin_bit_cast(double2, va[q]);                            \
+        const double2 y = __builtin_bit_cast(double2, vo[q]);                            \
+        st16(&As[b_][a_r][a_k + q * E], __builtin_bit_cast(uint4, make_double2(x.x - y.x, x.y - y.y))); \
       }                                                                                   \
-    } else {                                                                              \
-      _Pragma("unroll") for (int p = 0; p < P; ++p)                                      \
-        _Pragma("unroll") for (int q = 0; q < AV; ++q) st16(&As[b_][p][a_r][a_k + q * 8], va[p][q]); \
     }                                                                                     \
-    _Pragma("unroll") for (int p = 0; p < P; ++p)                                        \
-      _Pragma("unroll") for (int q = 0; q < BV; ++q) st16(&Bs[b_][p][b_r][b_k + q * BE], vb[p][q]); \
+    _Pragma("unroll") for (int q = 0; q < BV; ++q) st16(&Bs[b_][b_r][b_k + q * E], vb[q]); \
   } while (0)
 
   using Acc = typename std::conditional<MODE == MM_FP64, f64x4, f32x4>::type;
@@ -225,59 +195,26 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   DE_ROT_STASH(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    const int buf = NBUF == 2 ? (kt & 1) : 0;
+    const int buf = kt & 1;
     if (kt + 1 < nk) DE_ROT_FETCH(static_cast<int64_t>(kt + 1) * KT);
-    if constexpr (P == 1) {
 #pragma unroll
-      for (int s = 0; s < KT / 4; ++s) {
-        T af[WM], bf[WN];
+    for (int s = 0; s < KT / 4; ++s) {
+      T af[WM], bf[WN];
 #pragma unroll
-        for (int m = 0; m < WM; ++m) af[m] = As[buf][0][wm * (BM / 2) + m * 16 + lane % 16][4 * s + lane / 16];
+      for (int m = 0; m < WM; ++m) af[m] = As[buf][wm * (BM / 2) + m * 16 + lane % 16][4 * s + lane / 16];
 #pragma unroll
-        for (int n = 0; n < WN; ++n) bf[n] = Bs[buf][0][wn * (BN / 2) + n * 16 + lane % 16][4 * s + lane / 16];
+      for (int n = 0; n < WN; ++n) bf[n] = Bs[buf][wn * (BN / 2) + n * 16 + lane % 16][4 * s + lane / 16];
 #pragma unroll
-        for (int m = 0; m < WM; ++m)
+      for (int m = 0; m < WM; ++m)
 #pragma unroll
-          for (int n = 0; n < WN; ++n) {
-            if constexpr (MODE == MM_FP64)
-              acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m], bf[n], acc[m][n], 0, 0, 0);
-            else
-              acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[m], bf[n], acc[m][n], 0, 0, 0);
-          }
-      }
-    } else {
-      bf16x8 af[P][WM], bfr[P][WN];
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-#pragma unroll
-        for (int m = 0; m < WM; ++m)
-          af[p][m] = *reinterpret_cast<const bf16x8*>(
-              &As[buf][p][wm * (BM / 2) + m * 16 + lane % 16][8 * (lane / 16)]);
-#pragma unroll
-        for (int n = 0; n < WN; ++n)
-          bfr[p][n] = *reinterpret_cast<const bf16x8*>(
-              &Bs[buf][p][wn * (BN / 2) + n * 16 + lane % 16][8 * (lane / 16)]);
-      }
-      // piece products, smallest first; the product loop is outermost so that
-      // consecutive matrix-core ops use different accumulators
-      constexpr int NPR = P == 3 ? 6 : 3;
-      constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
-      constexpr int P0 = P == 3 ? 0 : 3;
-#pragma unroll
-      for (int q = 0; q < NPR; ++q)
-#pragma unroll
-        for (int m = 0; m < WM; ++m)
-#pragma unroll
-          for (int n = 0; n < WN; ++n)
-            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PA[P0 + q]][m], bfr[PB[P0 + q]][n],
-                                                                acc[m][n], 0, 0, 0);
+        for (int n = 0; n < WN; ++n) {
+          if constexpr (MODE == MM_FP64)
+            acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m], bf[n], acc[m][n], 0, 0, 0);
+          else
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[m], bf[n], acc[m][n], 0, 0, 0);
+        }
     }
-    if constexpr (NBUF == 1) {
-      __syncthreads();  // every wave is done with the slice before it is replaced
-      if (kt + 1 < nk) DE_ROT_STASH(0);
-    } else {
-      if (kt + 1 < nk) DE_ROT_STASH(buf ^ 1);
-    }
+    if (kt + 1 < nk) DE_ROT_STASH(buf ^ 1);
     __syncthreads();
   }
 
@@ -333,6 +270,222 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   }
 }
 
+// ---- split-bf16 product -----------------------------------------------------
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N-1>): indices
+// known at compile time, so the register arrays they index stay in registers.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Pieces multiplied by cross product Q of a P-piece split: (A piece, B
+// piece), smallest products first: hi*lo terms before hi*hi.
+template <int P, int Q> struct SplitProd {
+  static constexpr int q = P == 3 ? Q : Q + 3;
+  static constexpr int a = q == 0 ? 2 : q == 1 ? 1 : q == 2 ? 0 : q == 3 ? 1 : q == 4 ? 0 : 0;
+  static constexpr int b = q == 0 ? 0 : q == 1 ? 1 : q == 2 ? 2 : q == 3 ? 0 : q == 4 ? 1 : 0;
+};
+
+// The LDS slices hold rows of KT bf16 (KT / 8 chunks of 16 bytes) with the
+// chunk index XOR-ed by a function of the row, so that the 16-byte fragment
+// reads of consecutive rows at one k fall into different banks without
+// padding: chunk kc of row r sits at kc ^ swz(r).
+template <int KT>
+__device__ __forceinline__ int swz(int row) {
+  constexpr int KC = KT / 8, R128 = 64 / KT > 0 ? 64 / KT : 1;  // rows per 128 bytes
+  return (row / R128) % KC;
+}
+
+// Split-bf16 product, one BM x BN tile of Z per block of (BM/64) x (BN/64)
+// waves, each wave a 64x64 sub-tile as MF x MF matrix-core tiles (MF = 16:
+// 16x16x32, MF = 32: 32x32x16).  The A pieces come from the piece planes of
+// the rows (apc), the B pieces from the split M.  K advances KT columns per
+// step through two LDS buffers: the next slice goes into registers at the
+// start of a step and into the other buffer at its end, one barrier apart.
+// What the split product reads of a run, passed by value (kernel arguments
+// rather than loads from the run record keep the staged slices in registers).
+struct SplitArgs {
+  const __bf16* apc;   // A pieces: plane p, row i at apc + (p N + i) ldk
+  const __bf16* B[3];  // M pieces, rows padded to a multiple of 256, pitch ldk
+  const float* w;      // D weights
+  float* part;         // rows x ntile partial sums
+  int64_t N, D, ldk;
+  int32_t ntile;
+};
+
+template <int P, int BM, int BN, int KT, int MF>
+__global__ void __launch_bounds__((BM / 64) * (BN / 64) * 64)
+k_rot_gemm_split(SplitArgs Pr, int64_t rows) {
+  constexpr int WNV = BN / 64, NT = (BM / 64) * WNV * 64;
+  constexpr int KC = KT / 8;                       // 16-byte chunks per slice row
+  constexpr int AU = BM * KC / NT, BU = BN * KC / NT;  // chunks per thread and piece
+  static_assert(AU * NT == BM * KC && BU * NT == BN * KC, "whole chunks per thread");
+  static_assert(MF == 32 ? KT % 16 == 0 : KT % 32 == 0, "k steps of the matrix-core form");
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][P][BM * KT];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][P][BN * KT];
+  __shared__ float red[WNV][BM];
+
+  const int64_t D = Pr.D, ldk = Pr.ldk;
+  const int ntm = static_cast<int>((rows + BM - 1) / BM);
+  const int ntn = static_cast<int>((D + BN - 1) / BN);
+  const int nb = ntm * ntn;
+  int b = blockIdx.x;
+  if (nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;  // a contiguous range of tiles per XCD
+  const int tm = b / ntn, tn = b % ntn;
+  const int64_t row0 = static_cast<int64_t>(tm) * BM, col0 = static_cast<int64_t>(tn) * BN;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wm = wave / WNV, wn = wave % WNV;
+
+  // thread t moves chunks u = t + j NT of every piece: row u / KC, chunk u % KC
+  const __bf16* apc = Pr.apc;
+  const int64_t plane = Pr.N * ldk;
+  int64_t oa[AU], ob[BU];
+  int la[AU], lb[BU];
+#pragma unroll
+  for (int j = 0; j < AU; ++j) {
+    const int u = tid + j * NT, r = u / KC, kc = u % KC;
+    oa[j] = min(row0 + r, rows - 1) * ldk + kc * 8;
+    la[j] = r * KT + (kc ^ swz<KT>(r)) * 8;
+  }
+#pragma unroll
+  for (int j = 0; j < BU; ++j) {
+    const int u = tid + j * NT, r = u / KC, kc = u % KC;
+    ob[j] = (col0 + r) * ldk + kc * 8;  // rows of the M pieces are padded to a multiple of 256
+    lb[j] = r * KT + (kc ^ swz<KT>(r)) * 8;
+  }
+  uint4 va[P][AU], vb[P][BU];
+#define DE_SPLIT_FETCH(K0)                                                                    \
+  do {                                                                                        \
+    const int64_t k0_ = (K0);                                                                 \
+    _Pragma("unroll") for (int p = 0; p < P; ++p) {                                          \
+      _Pragma("unroll") for (int j = 0; j < AU; ++j)                                         \
+        va[p][j] = *reinterpret_cast<const uint4*>(apc + p * plane + oa[j] + k0_);            \
+      _Pragma("unroll") for (int j = 0; j < BU; ++j)                                         \
+        vb[p][j] = *reinterpret_cast<const uint4*>(Pr.B[p] + ob[j] + k0_);                    \
+    }                                                                                         \
+  } while (0)
+#define DE_SPLIT_STASH(BUF)                                                                   \
+  do {                                                                                        \
+    const int b_ = (BUF);                                                                     \
+    _Pragma("unroll") for (int p = 0; p < P; ++p) {                                          \
+      _Pragma("unroll") for (int j = 0; j < AU; ++j)                                         \
+        *reinterpret_cast<uint4*>(&As[b_][p][la[j]]) = va[p][j];                              \
+      _Pragma("unroll") for (int j = 0; j < BU; ++j)                                         \
+        *reinterpret_cast<uint4*>(&Bs[b_][p][lb[j]]) = vb[p][j];                              \
+    }                                                                                         \
+  } while (0)
+
+  constexpr int NPR = P == 3 ? 6 : 3;
+  constexpr int SM = 64 / MF;  // matrix-core tiles per wave side
+  using Acc = typename std::conditional<MF == 32, f32x16, f32x4>::type;
+  Acc acc[SM][SM];
+#pragma unroll
+  for (int m = 0; m < SM; ++m)
+#pragma unroll
+    for (int n = 0; n < SM; ++n) acc[m][n] = Acc{};
+
+  const int nk = static_cast<int>((D + KT - 1) / KT);
+  DE_SPLIT_FETCH(0);
+  DE_SPLIT_STASH(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    // Fetched and stored on every step (the last one re-fetches its own slice
+    // into the unused buffer): no branch around them keeps va, vb in registers.
+    DE_SPLIT_FETCH(static_cast<int64_t>(kt + 1 < nk ? kt + 1 : kt) * KT);
+    constexpr int KS = MF == 32 ? 16 : 32;  // k per matrix-core op
+#pragma unroll
+    for (int ks = 0; ks < KT / KS; ++ks) {
+      bf16x8 fa[P][SM], fb[P][SM];
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int m = 0; m < SM; ++m) {
+          const int ra = wm * 64 + m * MF + lane % MF;
+          const int rb = wn * 64 + m * MF + lane % MF;
+          const int kc = ks * (KS / 8) + lane / MF;
+          fa[p][m] = *reinterpret_cast<const bf16x8*>(&As[buf][p][ra * KT + (kc ^ swz<KT>(ra)) * 8]);
+          fb[p][m] = *reinterpret_cast<const bf16x8*>(&Bs[buf][p][rb * KT + (kc ^ swz<KT>(rb)) * 8]);
+        }
+      // the product loop is outermost, so consecutive matrix-core ops use
+      // different accumulators
+      static_for<NPR>([&](auto qc) {
+        constexpr int ia = SplitProd<P, decltype(qc)::value>::a;
+        constexpr int ib = SplitProd<P, decltype(qc)::value>::b;
+#pragma unroll
+        for (int m = 0; m < SM; ++m)
+#pragma unroll
+          for (int n = 0; n < SM; ++n) {
+            if constexpr (MF == 32)
+              acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[ia][m], fb[ib][n], acc[m][n], 0, 0, 0);
+            else
+              acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[ia][m], fb[ib][n], acc[m][n], 0, 0, 0);
+          }
+      });
+    }
+    DE_SPLIT_STASH(buf ^ 1);
+    __syncthreads();
+  }
+#undef DE_SPLIT_FETCH
+#undef DE_SPLIT_STASH
+
+  // ---- epilogue: sum_n w_n z_in^2 over this block's columns ----
+  constexpr int NR = MF == 32 ? 16 : 4;  // accumulator registers per tile
+  const float* w = Pr.w;
+  float rs[SM][NR];
+#pragma unroll
+  for (int m = 0; m < SM; ++m)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) rs[m][r] = 0.f;
+#pragma unroll
+  for (int n = 0; n < SM; ++n) {
+    const int64_t k = col0 + wn * 64 + n * MF + lane % MF;
+    const float wk = k < D ? w[k] : 0.f;
+#pragma unroll
+    for (int m = 0; m < SM; ++m)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const float z = acc[m][n][r];
+        rs[m][r] += wk * z * z;
+      }
+  }
+  // reduce over the MF lanes that share a row (fixed butterfly order)
+#pragma unroll
+  for (int m = 0; m < SM; ++m)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      float v = rs[m][r];
+#pragma unroll
+      for (int off = 1; off < MF; off <<= 1) v += __shfl_xor(v, off);
+      rs[m][r] = v;
+    }
+  if (lane % MF == 0) {
+#pragma unroll
+    for (int m = 0; m < SM; ++m)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int rr = MF == 32 ? 8 * (r / 4) + 4 * (lane / 32) + (r % 4) : (lane / 16) * 4 + r;
+        red[wn][wm * 64 + m * MF + rr] = rs[m][r];
+      }
+  }
+  __syncthreads();
+  // one partial per 128 columns (two wave columns), whatever the tile width,
+  // so every tile shape writes the same partial sums
+  constexpr int PG = BN / 128;
+  float* part = Pr.part;
+  for (int e = tid; e < BM * PG; e += NT) {
+    const int rr = e % BM, q = e / BM;
+    const int64_t i = row0 + rr;
+    const int col = tn * PG + q;
+    if (i < rows && col < Pr.ntile) part[i * Pr.ntile + col] = red[2 * q][rr] + red[2 * q + 1][rr];
+  }
+}
+
 // Sum of the partials of row i in tile order.
 template <typename T>
 __device__ __forceinline__ T row_total(const RunDev& P, int64_t i, int ntn) {
@@ -342,7 +495,7 @@ __device__ __forceinline__ T row_total(const RunDev& P, int64_t i, int ntn) {
   return canon(f);
 }
 
-// Greedy selection on the trials of generation g (Alg 2 lines 11-14).
+// Greedy selection on the trials of generation g (Alg 2's selection).
 template <typename T>
 __global__ void k_rot_select(const RunDev* __restrict__ runs, int32_t run, int ntn, GenNo gn) {
   const uint32_t gnew = gen_value(gn);
@@ -373,7 +526,7 @@ __global__ void k_rot_store(const RunDev* __restrict__ runs, int32_t run, int nt
   out[i] = row_total<T>(P, i, ntn);
 }
 
-// M pieces (rows padded to a multiple of 128, columns to ldk, zero filled)
+// M pieces (rows padded to a multiple of 256, columns to ldk, zero filled)
 // and the weights 10^(6k/(D-1)).
 template <int MODE>
 __global__ void k_rot_prepare(RunDev Pr, int64_t rows_pad) {
@@ -419,10 +572,10 @@ __global__ void k_rot_stage(T* __restrict__ dst, int64_t ld, const T* __restrict
 static inline unsigned nb(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
 
 static int tile_n_of(int mode) { return mode == MM_FP64 ? MM<MM_FP64>::BN : 128; }
-static int tile_m_of(int mode) { return mode == MM_FP64 ? MM<MM_FP64>::BM : 128; }
+static int tile_m_of(int mode) { return mode == MM_FP64 ? MM<MM_FP64>::BM : MM<MM_FP32>::BM; }
 
 hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s) {
-  const int64_t rows_pad = (h.D + 127) / 128 * 128;
+  const int64_t rows_pad = (h.D + 255) / 256 * 256;
   const int64_t n = rows_pad * h.ldk;
   switch (h.mm) {
     case MM_FP64: hipLaunchKernelGGL(k_rot_prepare<MM_FP64>, dim3(nb(n, 256)), dim3(256), 0, s, h, rows_pad); break;
@@ -440,24 +593,65 @@ hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Tile shapes of the split-bf16 product (BM x BN block tile, KT, matrix-core
+// form MF) for P pieces: option 1 is the default, 2 and 3 the runners-up of a
+// sweep on MI355X at 4096 x 2048 x 2048 (rows, D, D); the tuner picks among
+// them per shape.
+template <int P, int OPT> struct SplitShape;
+template <> struct SplitShape<3, 1> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 16; };
+template <> struct SplitShape<3, 2> { static constexpr int BM = 128, BN = 256, KT = 32, MF = 16; };
+template <> struct SplitShape<3, 3> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 32; };
+template <> struct SplitShape<2, 1> { static constexpr int BM = 128, BN = 128, KT = 32, MF = 16; };
+template <> struct SplitShape<2, 2> { static constexpr int BM = 128, BN = 256, KT = 32, MF = 16; };
+template <> struct SplitShape<2, 3> { static constexpr int BM = 128, BN = 128, KT = 32, MF = 32; };
+
+template <int P, int OPT>
+static void launch_split_gemm(const SplitArgs& a, int64_t rows, hipStream_t s) {
+  using S = SplitShape<P, OPT>;
+  const int64_t blocks = ((rows + S::BM - 1) / S::BM) * ((a.D + S::BN - 1) / S::BN);
+  hipLaunchKernelGGL((k_rot_gemm_split<P, S::BM, S::BN, S::KT, S::MF>), dim3(blocks),
+                     dim3((S::BM / 64) * (S::BN / 64) * 64), 0, s, a, rows);
+}
+
+template <int P>
+static void launch_split_gemm(const RunDev& h, int64_t rows, hipStream_t s) {
+  SplitArgs a;
+  a.apc = static_cast<const __bf16*>(h.apc);
+  for (int p = 0; p < 3; ++p) a.B[p] = static_cast<const __bf16*>(h.B[p]);
+  a.w = static_cast<const float*>(h.w);
+  a.part = static_cast<float*>(h.part);
+  a.N = h.N;
+  a.D = h.D;
+  a.ldk = h.ldk;
+  a.ntile = h.ntile;
+  switch (h.tile) {
+    case 2: launch_split_gemm<P, 2>(a, rows, s); break;
+    case 3: launch_split_gemm<P, 3>(a, rows, s); break;
+    default: launch_split_gemm<P, 1>(a, rows, s); break;
+  }
+}
+
 // split: write the bf16 pieces of the row source first (split-bf16 modes);
 // the trial kernel of a generation writes them itself.
 static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, GenNo gh,
                        int64_t rows, hipStream_t s, bool split = true) {
-  if (split && (h.mm == MM_BF16X3 || h.mm == MM_BF16X6)) {
-    const unsigned sb = nb(rows * h.ldk / 8, 256);
-    if (h.mm == MM_BF16X3)
-      hipLaunchKernelGGL(k_rot_split<2>, dim3(sb), dim3(256), 0, s, runs, run, src, gh, rows);
-    else
-      hipLaunchKernelGGL(k_rot_split<3>, dim3(sb), dim3(256), 0, s, runs, run, src, gh, rows);
+  if (h.mm == MM_BF16X3 || h.mm == MM_BF16X6) {
+    if (split) {
+      const unsigned sb = nb(rows * h.ldk / 8, 256);
+      if (h.mm == MM_BF16X3)
+        hipLaunchKernelGGL(k_rot_split<2>, dim3(sb), dim3(256), 0, s, runs, run, src, gh, rows);
+      else
+        hipLaunchKernelGGL(k_rot_split<3>, dim3(sb), dim3(256), 0, s, runs, run, src, gh, rows);
+    }
+    if (h.mm == MM_BF16X3) launch_split_gemm<2>(h, rows, s);
+    else launch_split_gemm<3>(h, rows, s);
+    return hipGetLastError();
   }
   const int bm = tile_m_of(h.mm), bn = tile_n_of(h.mm);
   const int64_t blocks = ((rows + bm - 1) / bm) * ((h.D + bn - 1) / bn);
   switch (h.mm) {
     case MM_FP64: hipLaunchKernelGGL(k_rot_gemm<MM_FP64>, dim3(blocks), dim3(256), 0, s, runs, run, src, gh, rows); break;
     case MM_FP32: hipLaunchKernelGGL(k_rot_gemm<MM_FP32>, dim3(blocks), dim3(256), 0, s, runs, run, src, gh, rows); break;
-    case MM_BF16X3: hipLaunchKernelGGL(k_rot_gemm<MM_BF16X3>, dim3(blocks), dim3(256), 0, s, runs, run, src, gh, rows); break;
-    case MM_BF16X6: hipLaunchKernelGGL(k_rot_gemm<MM_BF16X6>, dim3(blocks), dim3(256), 0, s, runs, run, src, gh, rows); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

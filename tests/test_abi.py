@@ -45,7 +45,7 @@ def test_workspace_size_and_validation(lib):
     assert big >= 2 * 2048 * 1024 * 8  # two padded FP64 population buffers
     bad = [good(N=3), good(D=0), good(CR=1.5), good(CR=float("nan")), good(F=-1.0),
            good(F=float("inf")), good(lo=1.0, hi=1.0), good(N=1 << 21), good(tpr=96)]
-    for field, v in (("base", 4), ("base", -1), ("shuffle", 2), ("wb", 3), ("reserved", 1)):
+    for field, v in (("base", 4), ("base", -1), ("shuffle", 2), ("wb", 3), ("tile", 1), ("tile", 4)):
         keep0: list = []
         d0 = de._desc(good(), keep0)
         setattr(d0, field, v)

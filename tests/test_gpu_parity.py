@@ -241,7 +241,7 @@ def test_two_statistic_best_and_many_generations(name):
         assert (idx, g) == (ridx, rg)
 
 
-# ---- base index schemes (Alg 3-6) and the shuffle of Alg 2 line 5 ----------
+# ---- base index schemes (Alg 3-6) and the shuffle of Alg 2 -------------------
 
 @pytest.mark.parametrize("shuffle", [False, True])
 @pytest.mark.parametrize("base", ["classic", "random", "offset", "perm"])
@@ -294,6 +294,57 @@ def test_shuffled_graph_replay_matches_direct_launches():
     assert ga == gb == 167
     assert np.array_equal(pa, pb) and np.array_equal(fa, fb)
     assert a.best(0)[:3] == b.best(0)[:3]
+
+
+# ---- exp / NEC rows longer than 4096 elements: streamed, not register-held ---
+
+def streamed(fn, **kw):
+    base = {"rastrigin": rast(), "rosenbrock": rosen(), "sphere": c1("nec"),
+            "ackley": table2("ackley"), "griewank": table2("griewank")}[fn]
+    d = dict(base, D=5003, N=10, CR=0.99, xo="nec")
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("fn", ["rastrigin", "rosenbrock", "sphere", "ackley", "griewank"])
+@pytest.mark.parametrize("xo,impl,dtype", [("nec", "lane", "fp32"), ("exp", "scan", "fp64"),
+                                           ("nec", "lane", "fp64")])
+def test_streamed_rows(fn, xo, impl, dtype):
+    # CR 0.99: runs of ~100 elements, many of them wrapping past D - 1
+    run_parity(streamed(fn, xo=xo, exp_impl=impl, dtype=dtype), 4)
+
+
+@pytest.mark.parametrize("fn", ["rastrigin", "rosenbrock"])
+def test_streamed_row_width_invariance(fn):
+    cfg = streamed(fn, D=4101, N=12, CR=0.9)
+    outs = []
+    for tpr in (64, 128, 256, 512, 1024):
+        gpu = DE([dict(cfg, tpr=tpr)])
+        tr = gpu.trace(0)
+        gpu.generation(1)
+        outs.append((tr["idx"].cpu().numpy().copy(), tr["trial"].cpu().numpy().copy(),
+                     tr["ftrial"].cpu().numpy().astype(np.float64)))
+        gpu.close()
+    ref = oracle_run(cfg)
+    rt = ref.generation(1, trace=True)
+    phi = oracle.fitness_phi(fn, rt["trial"], ref.shift())
+    for o in outs:
+        assert np.array_equal(o[0][:, :5], rt["idx"][:, :5])
+        assert np.array_equal(o[1], rt["trial"])
+        assert np.all(np.abs(o[2] - rt["ftrial"]) <= tol_of(cfg) * phi)
+
+
+def test_streamed_write_back_modes_agree():
+    base = streamed("rosenbrock", D=4500, N=16, CR=0.95, dtype="fp32")
+    outs = []
+    for wb in ("whole", "partial", "auto"):
+        gpu = DE([dict(base, wb=wb)])
+        gpu.generation(60)
+        outs.append((gpu.state(0), gpu.best(0)[:3]))
+        gpu.close()
+    for (st, b) in outs[1:]:
+        assert np.array_equal(st[0], outs[0][0][0]) and np.array_equal(st[1], outs[0][0][1])
+        assert b == outs[0][1]
 
 
 # ---- partial write-back: winners write only where the buffers differ -------
@@ -359,6 +410,26 @@ def test_rotated_ellipsoid(mm, dtype, xo):
     run_parity(ell(mm, dtype, xo=xo), 3, rot=rot)
 
 
+@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("mm", ["bf16x6", "bf16x3"])
+def test_rotated_tiles(mm, tile):
+    """Every tile shape of the split-bf16 product at a D that is ragged against
+    128- and 256-wide tiles; shapes 1 and 2 use the same matrix-core form, so
+    their fitness values agree bit for bit."""
+    D = 300
+    rot = rotation(D, 6)
+    run_parity(ell(mm, "fp32", D=D, N=100, tile=tile), 3, rot=rot)
+    if tile == 2:
+        outs = []
+        for t in (1, 2):
+            gpu = DE([ell(mm, "fp32", D=D, N=100, tile=t)], rot)
+            tr = gpu.trace(0)
+            gpu.generation(2)
+            outs.append(tr["ftrial"].cpu().numpy().copy())
+            gpu.close()
+        assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("mm", ["fp32", "bf16x6"])
 def test_rotated_ellipsoid_exp_job(mm):
     rot = rotation(96, 1)
@@ -384,6 +455,44 @@ def test_batched_runs_match_independent_oracles():
 
 
 # ---- other entry points -----------------------------------------------------
+
+def test_batched_512_table_sampled_runs():
+    """The benchmark's full table of 512 runs in one handle: six runs spread
+    over the table are traced and checked, each against its own oracle run,
+    for two generations."""
+    from paper_2101_06599_amd import synth
+    cfgs = synth.batch_table(512, seed=0)
+    gpu = DE(cfgs)
+    sample = [0, 97, 211, 333, 402, 511]
+    refs = {r: oracle_run(cfgs[r], run=r) for r in sample}
+    for r in sample:
+        pop_g, _, _ = gpu.state(r)
+        assert np.array_equal(pop_g.astype(np.float64), refs[r].state()[0]), f"run {r} init"
+    traces = {r: gpu.trace(r) for r in sample}
+    for _ in range(2):
+        gpu.generation(1)
+        for r in sample:
+            compare_generation(gpu, refs[r], cfgs[r], run=r, trace=traces[r], stepped=True)
+
+
+@pytest.mark.parametrize("block", [100, 500])
+def test_graph_blocks_of_any_length(block):
+    """Graphs of `block` generations (best-so-far updated every 64 and at the
+    end of a block) give the states and best records of direct launches."""
+    from paper_2101_06599_amd import synth
+    cfgs = synth.batch_table(n_runs=4, seed=3, max_D=200, max_N=40)
+    a, b = DE(cfgs), DE(cfgs)
+    b.graph(block)
+    for n in (2 * block + 37, block):
+        a.generation(n)
+        b.generation(n)
+    for r in range(len(cfgs)):
+        pa, fa, ga = a.state(r)
+        pb, fb, gb = b.state(r)
+        assert ga == gb == 3 * block + 37
+        assert np.array_equal(pa, pb) and np.array_equal(fa, fb)
+        assert a.best(r)[:3] == b.best(r)[:3]
+
 
 @pytest.mark.parametrize("cfg", [rast(dtype="fp64"), rast(dtype="fp32", fn="rosenbrock"),
                                  c1("bin")])
@@ -522,6 +631,23 @@ def test_best_is_fp64_recompute_of_best_row():
     assert fit[idx] == fit.min()
     ref = oracle_run(cfg)
     fr = oracle.fitness("rastrigin", x.astype(np.float64), ref.shift())
+    assert abs(f - fr) <= 1e-12 * fr
+
+
+@pytest.mark.parametrize("mm,dtype,D", [("bf16x6", "fp32", 300), ("fp64", "fp64", 257),
+                                        ("fp32", "fp32", 2)])
+def test_best_rotated_is_fp64_recompute(mm, dtype, D):
+    """de_best on the rotated function: the FP64 value of the best stored row
+    with FP64 M and weights (one wavefront per z_k, then a fixed-order sum)."""
+    rot = rotation(D, 5)
+    cfg = ell(mm, dtype, D=D, N=64)
+    gpu = DE([cfg], rot)
+    gpu.generation(4)
+    f, idx, g, x = gpu.best(0)
+    pop, fit, _ = gpu.state(0)
+    assert np.array_equal(pop[idx], x) and fit[idx] == fit.min()
+    ref = oracle_run(cfg, rot=rot)
+    fr = oracle.fitness("ellipsoid_rot", x.astype(np.float64), ref.shift(), rot)
     assert abs(f - fr) <= 1e-12 * fr
 
 
