@@ -5,25 +5,34 @@
 A step is one generation of the headline workload: shifted Rastrigin,
 D = 1000, N = 2048, F = 0.5, CR = 0.9, NEC crossover, FP64 (index draws,
 crossover mask, masked DE/rand/1 mutation, fitness, greedy selection and the
-best-so-far update, with the population resident in HBM).  `value` is
-pop*dim*gen/s = N * D * K / (time of K generations).
+best-so-far update, with the population resident in device memory).  `value`
+is pop*dim*gen/s = N * D * K / (time of K generations).
 
-The same JSON line carries:
-  roofline      the fused generation kernel's algorithmic bytes per launch
-                over its event-timed average duration, against 8 TB/s;
-  cpu_baseline  the CPU oracle on a bounded sample of the same workload;
-  variants      bin / classic exp (three GPU mappings) / NEC x FP64 / FP32;
-  rosenbrock    shifted Rosenbrock D = 10000, N = 8192, FP32 (HBM-sized);
-  rotated       rotated ellipsoid D = 2048, N = 4096: product TFLOP/s per mode;
-  batched       512 independent NEC runs of uneven shape in one launch;
-  table1_masks  the crossover-only grid of Table 1 (masks written to HBM);
-  fig456_nec_vs_pexp  the NEC / p-exp mask sweep of Figs 4-6;
-  paper_runs    the three runs of Table 2 (Ackley, Griewank, Rosenbrock) end
-                to end, with best value and generation reached.
+The JSON line (one line on stdout) carries, after the standard fields, the
+paper's own experiments in short form (Table 1 masks, Figs 4-6, the Table 2
+runs), then the benchmark workloads (C1 sphere, C2 variants, C4 batched, C3
+rotated, C5 large Rosenbrock), the roofline of the headline kernel and the CPU
+oracle baseline, so that the end of the line holds the main figures.
+
+Byte bases of every `frac_*` figure (fraction of the 8 TB/s HBM peak):
+  frac_alg  algorithmic bytes s N D (2 + 3 rho): read the parent row, read the
+            three donors where the mask is set, write the trial row;
+  frac_min  bytes any design must move, s N D (1 + 3 rho + rho w): parent,
+            masked donors, and the masked elements of the w winners;
+  frac_ctr  FETCH_SIZE + WRITE_SIZE per launch from rocprofv3 counters
+            (profiles/traffic.json, only while the kernel sources are the ones
+            the counters were taken on), else null.
+frac_alg charges a trial write for every row while the kernels write only
+winners, so it can exceed frac_ctr; each is reported with its basis.
+
+Counter summaries: `python bench.py --counters DIR` prints per-kernel averages
+of rocprofv3 CSV output found under DIR (used for the files in profiles/).
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import math
@@ -38,6 +47,15 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
 
 
+def r4(x):
+    """Four significant digits (keeps the JSON line short)."""
+    if x is None or isinstance(x, (bool, int, str)):
+        return x
+    if not math.isfinite(x) or x == 0:
+        return x
+    return float(f"{x:.4g}")
+
+
 def rho(xo: str, D: int, CR: float) -> float:
     """Expected fraction of crossed elements (mask density)."""
     if xo == "bin":
@@ -48,19 +66,60 @@ def rho(xo: str, D: int, CR: float) -> float:
 
 
 def alg_bytes(xo, N, D, CR, esz):
-    """Algorithmic HBM bytes of one generation: read each parent row, read the
-    three donor rows where the mask is set, write the trial into the other
-    buffer: esz * N * D * (2 + 3 rho)."""
+    """Algorithmic bytes of one generation: esz N D (2 + 3 rho)."""
     return esz * N * D * (2.0 + 3.0 * rho(xo, D, CR))
 
 
-def lower_bytes(xo, N, D, CR, esz, win):
-    """Bytes the winners-only write-back needs: parent + masked donors +
-    winner rows."""
-    return esz * N * D * (1.0 + 3.0 * rho(xo, D, CR) + win)
+def min_bytes(xo, N, D, CR, esz, win):
+    """Bytes any design must move: esz N D (1 + 3 rho + rho w)."""
+    r = rho(xo, D, CR)
+    return esz * N * D * (1.0 + 3.0 * r + r * win)
+
+
+def source_sha():
+    """Hash of the kernel sources (counter figures are void once it changes)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2101_06599_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+_TRAFFIC = None
+
+
+def traffic(tag):
+    """Counter bytes per launch of a kernel, if measured on these sources."""
+    global _TRAFFIC
+    if _TRAFFIC is None:
+        path = os.path.join(ROOT, "profiles", "traffic.json")
+        _TRAFFIC = json.load(open(path)) if os.path.exists(path) else {}
+    rec = _TRAFFIC.get(tag)
+    if not rec or rec.get("source_sha") != source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def fracs(tag, xo, N, D, CR, esz, win, kms):
+    sec = kms * 1e-3
+    ab = alg_bytes(xo, N, D, CR, esz)
+    mb = min_bytes(xo, N, D, CR, esz, win) if win is not None else None
+    tb = traffic(tag)
+    out = {"frac_alg": ab / sec / 1e9 / HBM_PEAK_GBS,
+           "frac_min": None if mb is None else mb / sec / 1e9 / HBM_PEAK_GBS,
+           "frac_ctr": None if tb is None else tb / sec / 1e9 / HBM_PEAK_GBS}
+    return {k: r4(v) for k, v in out.items()}
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
 
 
 def time_gens(gpu, K):
+    """Milliseconds for K generations (HIP events on the launch stream,
+    synchronised before and after)."""
     import torch
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -73,12 +132,11 @@ def time_gens(gpu, K):
 
 
 def kernel_ms(gpu, K):
-    """Average duration of the generation's main kernel (HIP events around each
-    launch on the launch stream)."""
-    import torch
+    """Average duration of the generation's main kernel (HIP events around the
+    launches on the launch stream)."""
     gpu.profile(True)
     gpu.generation(K)
-    torch.cuda.synchronize()
+    sync()
     ms, n = gpu.profile_read()
     gpu.profile(False)
     return ms / max(n, 1)
@@ -87,78 +145,33 @@ def kernel_ms(gpu, K):
 def winners(gpu, K, run=0):
     """Average fraction of rows replaced per generation over K generations."""
     import numpy as np
-    _, f0, _ = gpu.state(run)
-    wins = 0
+    wins, n = 0, 0
+    fa = gpu.fitness(run)
     for _ in range(K):
-        _, fa, _ = gpu.state(run)
         gpu.generation(1)
-        _, fb, _ = gpu.state(run)
+        fb = gpu.fitness(run)
         wins += int(np.count_nonzero(fb < fa))
-    return wins / (K * len(f0))
+        n += len(fa)
+        fa = fb
+    return wins / n
 
 
-def run_variant(cfg, K, W, prof_K, graph=False):
-    """Times K generations (direct launches, or replayed 64-generation graphs
-    when `graph`), then the main kernel's average duration with events."""
+def run_variant(cfg, K, W, prof_K, win_K=0):
     import paper_2101_06599_amd as de
     gpu = de.DE([cfg])
-    gpu.graph(graph)
     gpu.generation(W)
     ms = time_gens(gpu, K)
     kms = kernel_ms(gpu, prof_K)
-    f, idx, g, _ = gpu.best(0)
-    out = dict(ms_per_gen=ms / K, kernel_ms=kms,
-               pop_dim_gen_s=cfg["N"] * cfg["D"] * K / (ms / 1e3), best=f, best_gen=g)
-    return gpu, out
+    win = winners(gpu, win_K) if win_K else None
+    gpu.close()
+    return {"ms_per_gen": ms / K, "kernel_ms": kms, "win": win,
+            "pop_dim_gen_s": cfg["N"] * cfg["D"] * K / (ms / 1e3)}
 
 
-def traffic_from_profile(kernel_tag):
-    """HBM bytes per launch measured with rocprofv3 counters, if the kernel
-    source is unchanged since they were taken (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    rec = json.load(open(path)).get(kernel_tag)
-    if not rec:
-        return None
-    if rec.get("source_sha") != source_sha():
-        return None
-    return rec.get("bytes_per_launch")
+# ---- the paper's experiments (short form) -----------------------------------
 
-
-def source_sha():
-    h = hashlib.sha256()
-    for f in ("k_generation.hip", "de_device.h", "de_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2101_06599_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
-
-
-def cpu_baseline(cfg, seconds=15.0):
-    import oracle
-    kw = {k: cfg[k] for k in ("N", "D", "F", "CR", "xo", "fn", "dtype", "lo", "hi", "olo", "ohi",
-                              "seed")}
-    # the oracle's per-individual loops use OpenMP with the process's default
-    # thread count (OMP_NUM_THREADS, else the host's cores)
-    threads = oracle.set_threads(0)
-    r = oracle.Run(**kw)
-    t0 = time.perf_counter()
-    g = 0
-    while True:
-        r.generation(1)
-        g += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": cfg["N"] * cfg["D"] * g / dt, "unit": "pop*dim*gen/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{g} generations of the same workload (N={cfg['N']}, D={cfg['D']}, "
-                      f"{cfg['xo']}, {cfg['dtype']}) after initialisation, {threads} OpenMP "
-                      f"threads, {dt:.1f} s"}
-
-
-# Table 1 of the paper: total time (presumably seconds) of mask generation over
-# Cr in {0.2, 0.4, 0.6, 0.8, 1.0} x 100 repeats, CuPy on a GTX 760:
-# (D, Np) -> (CUDA-nec, CUDA-bin).
+# Table 1: total seconds of mask generation over Cr in {0.2, ..., 1.0} x 100
+# repeats, CuPy on a GTX 760: (D, Np) -> (CUDA-nec, CUDA-bin).
 PAPER_TABLE1 = {(10, 100): (1.76, 6.99), (10, 1000): (1.18, 0.64), (10, 10000): (1.34, 0.94),
                 (100, 100): (1.16, 0.66), (100, 1000): (1.23, 0.64), (100, 10000): (1.11, 1.36),
                 (1000, 100): (0.66, 0.56), (1000, 1000): (1.07, 1.00), (1000, 10000): (4.31, 4.56),
@@ -167,9 +180,8 @@ PAPER_TABLE1 = {(10, 100): (1.76, 6.99), (10, 1000): (1.18, 0.64), (10, 10000): 
 
 
 def time_masks(torch, de, run, out, reps):
-    """Seconds for masks of generations 1..reps of one run written to `out`:
-    the ABI call is made directly with prepared arguments, so the loop adds
-    little host time between the launches."""
+    """Seconds for masks of generations 1..reps of one run written to `out`
+    (the ABI is called directly, so the loop adds little host time)."""
     import ctypes as C
     h = de.DE([run])
     s = torch.cuda.current_stream()
@@ -189,54 +201,57 @@ def time_masks(torch, de, run, out, reps):
 
 
 def table1(torch, de, reps=100):
-    """The paper's crossover-only grid: masks of 100 generations per Cr, summed
-    over the five Cr values, with the masks written to device memory."""
-    res = {}
+    """Table 1's grid: seconds for masks of 100 generations per Cr, summed over
+    the five Cr values (nec, bin, exp-scan), with the paper's CUDA times as the
+    speed-up basis; and the 100 MB launch at N = D = 10^4 as a fraction of the
+    HBM write bandwidth."""
+    res, sp = {}, []
+    big = {}
     for (D, N), (p_nec, p_bin) in PAPER_TABLE1.items():
-        row = {}
-        for xo, paper in (("nec", p_nec), ("bin", p_bin), ("exp", None)):
-            total = 0.0
-            out = torch.empty((N, D), dtype=torch.uint8, device="cuda:0")
+        row = []
+        out = torch.empty((N, D), dtype=torch.uint8, device="cuda:0")
+        for xo in ("nec", "bin", "exp"):
+            tot = 0.0
             for CR in (0.2, 0.4, 0.6, 0.8, 1.0):
-                total += time_masks(torch, de, dict(N=N, D=D, CR=CR, xo=xo, exp_impl="scan",
-                                                    fn="sphere", dtype="fp32", seed=0), out, reps)
-            del out
-            row[xo] = {"total_s": total}
-            if paper is not None:
-                row[xo].update(paper_cuda_s=paper, speedup_vs_paper=paper / total)
+                t = time_masks(torch, de, dict(N=N, D=D, CR=CR, xo=xo, exp_impl="scan",
+                                               fn="sphere", dtype="fp32", seed=0), out, reps)
+                tot += t
+                if (D, N) == (10000, 10000):
+                    big.setdefault(xo, []).append(t / reps)
+            row.append(r4(tot))
+        del out
         res[f"D{D}_N{N}"] = row
-    return res
+        sp += [p_nec / row[0], p_bin / row[1]]
+    per = {xo: sum(v) / len(v) for xo, v in big.items()}
+    return {"cols": "nec, bin, exp-scan seconds (5 Cr x 100 generations)", "cells": res,
+            "speedup_vs_paper_cuda": [r4(min(sp)), r4(max(sp))],
+            "n10000_d10000_us_per_launch": {k: r4(v * 1e6) for k, v in per.items()},
+            "n10000_d10000_frac_write": {k: r4(1e8 / v / 1e9 / HBM_PEAK_GBS) for k, v in per.items()}}
 
 
 def fig456(torch, de, reps=100):
-    """Figs 4-6 of the paper: crossover-mask time of NEC against the classic
-    exponential crossover with one work-item per individual (p-exp), for
-    N in {100, 1000, 5000} and D from 2 to 5000, 100 generations per point.
-    The figures do not name Cr: each point sums Cr in {0.2, ..., 1.0} as
-    Table 1 does.  The wavefront-scan mapping of the classic crossover is
-    timed beside them."""
+    """Figs 4-6: mask time of the job-per-individual classic exponential
+    crossover (p-exp) and of the wavefront-scan one over NEC, N in {100, 1000,
+    5000}, D from 2 to 5000 (each point sums Cr in {0.2, ..., 1.0} like
+    Table 1)."""
     res = {}
     for N in (100, 1000, 5000):
-        for D in (2, 10, 50, 100, 500, 1000, 2000, 5000):
-            row = {}
-            for name, xo, impl in (("nec", "nec", "lane"), ("p_exp", "exp", "job"),
-                                   ("exp_scan", "exp", "scan")):
-                total = 0.0
-                out = torch.empty((N, D), dtype=torch.uint8, device="cuda:0")
-                for CR in (0.2, 0.4, 0.6, 0.8, 1.0):
-                    total += time_masks(torch, de, dict(N=N, D=D, CR=CR, xo=xo, exp_impl=impl,
-                                                        fn="sphere", dtype="fp32", seed=0),
-                                        out, reps)
-                row[name + "_s"] = total
-                del out
-            row["p_exp_over_nec"] = row["p_exp_s"] / row["nec_s"]
-            res[f"N{N}_D{D}"] = row
-    return res
+        ratios = []
+        for D in (2, 10, 100, 1000, 5000):
+            tt = {}
+            out = torch.empty((N, D), dtype=torch.uint8, device="cuda:0")
+            for name, xo, impl in (("nec", "nec", "lane"), ("pexp", "exp", "job"),
+                                   ("scan", "exp", "scan")):
+                tt[name] = sum(time_masks(torch, de, dict(N=N, D=D, CR=CR, xo=xo, exp_impl=impl,
+                                                          fn="sphere", dtype="fp32", seed=0),
+                                          out, reps) for CR in (0.2, 0.4, 0.6, 0.8, 1.0))
+            del out
+            ratios.append([D, r4(tt["pexp"] / tt["nec"]), r4(tt["scan"] / tt["nec"])])
+        res[f"N{N}"] = ratios
+    return {"cols": "D, p-exp/nec, exp-scan/nec (time ratios)", "points": res}
 
 
-# Tables 3-5 of the paper (Sec. 4, GTX 760, CuPy): the CUDA-DE rows,
-# variant -> (best value, generation of the best, seconds for the whole run).
-# "L" is the new exponential crossover (our "nec").
+# Tables 3-5 (Sec. 4, GTX 760, CuPy), CUDA-DE rows: (best value, best gen, s).
 PAPER_TABLE345 = {
     "ackley": {"nec": (2.62e-05, 29991, 323.97), "bin": (2.28e-04, 29983, 321.45)},
     "griewank": {"nec": (1.73e-16, 19936, 149.03), "bin": (2.22e-16, 6041, 143.95)},
@@ -245,40 +260,204 @@ PAPER_TABLE345 = {
 
 
 def paper_runs(torch, de, synth, seeds=(0, 1, 2, 3, 4)):
-    """The three runs of Table 2 end to end (every generation, FP64) over
-    several seeds: time per run and the best value and generation each seed
-    reaches.  The paper's CUDA-DE figures sit beside them as context (other
-    hardware, other random streams, one run each)."""
+    """The three runs of Table 2 end to end (every generation, FP64) over five
+    seeds: mean seconds per run, median best value, and the speed-up over the
+    paper's CUDA-DE time for the same run (other hardware, other streams)."""
     res = {}
     for name, base in synth.TABLE2.items():
         for xo in ("nec", "bin"):
-            times, vals, gens_best = [], [], []
+            times, vals = [], []
             for seed in seeds:
                 cfg = dict(base, xo=xo, seed=seed)
                 gens = cfg.pop("gens")
                 h = de.DE([cfg])
-                s = torch.cuda.current_stream()
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                torch.cuda.synchronize()
-                e0.record(s)
-                h.generation(gens)
-                e1.record(s)
-                torch.cuda.synchronize()
-                times.append(e0.elapsed_time(e1) / 1e3)
-                f, _, g, _ = h.best(0)
-                vals.append(f)
-                gens_best.append(g)
+                times.append(time_gens(h, gens) / 1e3)
+                vals.append(h.best(0)[0])
                 h.close()
-            pv, pg, pt = PAPER_TABLE345[name][xo]
             t = sum(times) / len(times)
-            res[f"{name}_D{base['D']}_N{base['N']}_{xo}"] = {
-                "generations": base["gens"], "seeds": list(seeds), "time_s_mean": t,
-                "us_per_gen": t / base["gens"] * 1e6, "best_values": vals,
-                "best_value_median": sorted(vals)[len(vals) // 2], "best_gens": gens_best,
-                "paper_cuda": {"best_value": pv, "best_gen": pg, "time_s": pt},
-                "speedup_vs_paper": pt / t}
-    return res
+            res[f"{name}_{xo}"] = [r4(t), r4(sorted(vals)[len(vals) // 2]),
+                                   r4(PAPER_TABLE345[name][xo][2] / t)]
+    return {"cols": "s per run, median best value, speed-up vs paper CUDA-DE", "runs": res}
+
+
+# ---- benchmark workloads -------------------------------------------------------
+
+def c1_sphere(synth):
+    """C1: sphere D = 10, N = 50, FP64, 100 generations per crossover."""
+    import paper_2101_06599_amd as de
+    out = {}
+    for name, xo, impl in (("bin", "bin", "lane"), ("exp", "exp", "lane"), ("exp-scan", "exp", "scan"),
+                           ("nec", "nec", "lane")):
+        cfg = dict(synth.SPHERE_D10, xo=xo, exp_impl=impl)
+        gpu = de.DE([cfg])
+        gpu.generation(10)
+        ms = time_gens(gpu, 100)
+        f = gpu.best(0)[0]
+        gpu.close()
+        out[name] = [r4(ms / 100 * 1e3), r4(cfg["N"] * cfg["D"] * 100 / (ms / 1e3)), r4(f)]
+    return {"cols": "us per generation, pop*dim*gen/s, best after 110 generations", "runs": out}
+
+
+def c2_variants(synth, K, W):
+    out = {}
+    for dtype in ("fp64", "fp32"):
+        es = 8 if dtype == "fp64" else 4
+        for xo, impl in (("nec", "lane"), ("bin", "lane"), ("exp", "scan"), ("exp", "lane"),
+                         ("exp", "job")):
+            cfg = dict(synth.RASTRIGIN_D1000, xo=xo, dtype=dtype, exp_impl=impl)
+            kk = K if impl != "job" else max(10, K // 10)
+            r = run_variant(cfg, kk, min(W, 10), prof_K=100, win_K=10)
+            name = f"{xo}{'' if xo != 'exp' else '-' + impl}_{dtype}"
+            d = {"ms": r4(r["ms_per_gen"]), "kernel_ms": r4(r["kernel_ms"]),
+                 "pdg_s": r4(r["pop_dim_gen_s"])}
+            d.update(fracs(f"c2_{name}", xo, cfg["N"], cfg["D"], cfg["CR"], es, r["win"],
+                           r["kernel_ms"]))
+            out[name] = d
+    for dtype in ("fp64", "fp32"):
+        nec = out[f"nec_{dtype}"]["ms"]
+        out[f"nec_over_bin_time_{dtype}"] = r4(nec / out[f"bin_{dtype}"]["ms"])
+        out[f"exp-job_over_nec_time_{dtype}"] = r4(out[f"exp-job_{dtype}"]["ms"] / nec)
+        out[f"exp-scan_over_nec_time_{dtype}"] = r4(out[f"exp-scan_{dtype}"]["ms"] / nec)
+    return out
+
+
+def c5_rosenbrock(synth):
+    """C5: shifted Rosenbrock D = 10^4, N = 8192, FP32 (2 x 328 MB of
+    population: beyond the 256 MB Infinity Cache)."""
+    out = {}
+    for xo, impl in (("nec", "lane"), ("bin", "lane"), ("exp", "scan")):
+        cfg = dict(synth.ROSENBROCK_D10000, xo=xo, exp_impl=impl)
+        r = run_variant(cfg, 100, 5, prof_K=50, win_K=5)
+        name = xo if xo != "exp" else "exp-scan"
+        d = {"ms": r4(r["ms_per_gen"]), "kernel_ms": r4(r["kernel_ms"]),
+             "pdg_s": r4(r["pop_dim_gen_s"])}
+        d.update(fracs(f"c5_{name}", xo, cfg["N"], cfg["D"], cfg["CR"], 4, r["win"],
+                       r["kernel_ms"]))
+        out[name] = d
+    out["nec_over_bin_time"] = r4(out["nec"]["ms"] / out["bin"]["ms"])
+    return out
+
+
+def c3_rotated(torch, synth):
+    """C3: rotated ellipsoid D = 2048, N = 4096: the product's time per
+    generation and its rate against the matrix-core peak of the type it
+    executes (split-bf16 executes 3 or 6 bf16 products)."""
+    rot = torch.as_tensor(synth.rotation(2048, 0), dtype=torch.float64, device="cuda:0")
+    out = {}
+    for mm, dtype, mdt, mult in (("bf16x6", "fp32", "bf16", 6), ("bf16x3", "fp32", "bf16", 3),
+                                 ("fp32", "fp32", "fp32", 1), ("fp64", "fp64", "fp64", 1)):
+        cfg = dict(synth.ELLIPSOID_D2048, xo="nec", dtype=dtype, mm=mm, rot=rot)
+        r = run_variant(cfg, 20, 2, prof_K=10)
+        flops = 2.0 * cfg["N"] * cfg["D"] ** 2
+        tf = flops / (r["kernel_ms"] * 1e-3) / 1e12
+        out[mm] = {"ms_per_gen": r4(r["ms_per_gen"]), "product_ms": r4(r["kernel_ms"]),
+                   "alg_tflops": r4(tf), "exec_tflops": r4(tf * mult),
+                   "mfma_frac": r4(tf * mult / MFMA_PEAK_TFLOPS[mdt])}
+    return out
+
+
+def c4_batched(synth):
+    """C4: 512 NEC runs of uneven shape, FP32, one launch per generation;
+    500 generations replayed from one captured graph, and direct launches."""
+    import paper_2101_06599_amd as de
+    cfgs = synth.batch_table(512, seed=0)
+    elems = sum(c["N"] * c["D"] for c in cfgs)
+    g2 = de.DE(cfgs)
+    g2.generation(5)
+    ms = time_gens(g2, 100)
+    kms = kernel_ms(g2, 50)
+    g2.close()
+    g3 = de.DE(cfgs)
+    g3.graph(500)
+    g3.generation(500)  # captures the 500-generation graph, replays it once
+    ms_graph = time_gens(g3, 500)
+    g3.close()
+    byt = sum(alg_bytes("nec", c["N"], c["D"], c["CR"], 4) for c in cfgs)
+    return {"runs": 512, "elements": elems, "ms_direct": r4(ms / 100), "kernel_ms": r4(kms),
+            "ms_graph500": r4(ms_graph / 500), "pdg_s_graph500": r4(elems * 500 / (ms_graph / 1e3)),
+            "pdg_s_direct": r4(elems * 100 / (ms / 1e3)),
+            "frac_alg": r4(byt / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS),
+            "frac_ctr": None if traffic("c4_batched") is None
+            else r4(traffic("c4_batched") / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS)}
+
+
+# ---- CPU oracle ------------------------------------------------------------------
+
+def _timed(fn):
+    t0 = time.perf_counter()
+    fn()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(synth, head, seconds):
+    """The oracle (plain sequential C, OpenMP over individuals) on bounded
+    samples: the headline workload with all host threads and with one, and
+    per-generation rates of the other workloads on prefixes (C1 whole, C5 one
+    generation, C3 one generation of 64 rows, C4 two generations of every run)."""
+    import numpy as np
+
+    import oracle
+    keys = ("N", "D", "F", "CR", "xo", "fn", "dtype", "lo", "hi", "olo", "ohi", "seed")
+    cores = oracle.set_threads(0)
+
+    def rate_head(threads, budget):
+        oracle.set_threads(threads)
+        r = oracle.Run(**{k: head[k] for k in keys})
+        g, t0 = 0, time.perf_counter()
+        while True:
+            r.generation(1)
+            g += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return head["N"] * head["D"] * g / (time.perf_counter() - t0), g
+
+    all_rate, g_all = rate_head(cores, seconds)
+    one_rate, g_one = rate_head(1, seconds / 2)
+    oracle.set_threads(cores)
+    pre = {}
+    c1 = dict(synth.SPHERE_D10, xo="nec")
+    r = oracle.Run(**{k: c1[k] for k in keys if k in c1})
+    pre["c1_nec_pdg_s"] = r4(c1["N"] * c1["D"] * 100 / _timed(lambda: r.generation(100)))
+    c5 = dict(synth.ROSENBROCK_D10000, xo="nec")
+    r = oracle.Run(**{k: c5[k] for k in keys if k in c5})
+    pre["c5_nec_pdg_s"] = r4(c5["N"] * c5["D"] / _timed(lambda: r.generation(1)))
+    del r
+    D = 2048
+    c3 = dict(synth.ELLIPSOID_D2048, N=64, xo="nec", dtype="fp32")
+    r = oracle.Run(rot=synth.rotation(D, 0), **{k: c3[k] for k in keys if k in c3})
+    pre["c3_gflops_64rows"] = r4(2.0 * 64 * D * D / _timed(lambda: r.generation(1)) / 1e9)
+    del r
+    runs = [oracle.Run(run=i, **{k: c[k] for k in keys if k in c})
+            for i, c in enumerate(synth.batch_table(512, seed=0))]
+    elems = sum(x.N * x.D for x in runs)
+    pre["c4_pdg_s"] = r4(elems * 2 / _timed(lambda: [x.generation(2) for x in runs]))
+    del runs
+    return {"value": r4(all_rate), "unit": "pop*dim*gen/s", "cores": cores, "kind": "oracle",
+            "sample": f"headline workload, {g_all} generations with {cores} OpenMP threads "
+                      f"(~{seconds:.0f} s); one-thread leg {g_one} generations",
+            "one_thread": r4(one_rate), "prefix_rates": pre}
+
+
+# ---- counter summaries -------------------------------------------------------------
+
+def counters_summary(d):
+    """Per-kernel averages of every rocprofv3 CSV under d (counter collection
+    and kernel-trace stats), as markdown tables."""
+    rows = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for rec in csv.DictReader(open(f)):
+            k = (rec["Kernel_Name"].split("(")[0], rec["Counter_Name"])
+            rows.setdefault(k, []).append(float(rec["Counter_Value"]))
+    if rows:
+        print("| kernel | counter | dispatches | mean |\n|---|---|---|---|")
+        for (kn, cn), v in sorted(rows.items()):
+            print(f"| `{kn}` | {cn} | {len(v)} | {sum(v) / len(v):.6g} |")
+    for f in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
+        print(f"\n{os.path.relpath(f, d)}:\n\n| kernel | calls | avg ns | min ns | max ns | % |")
+        print("|---|---|---|---|---|---|")
+        for rec in csv.DictReader(open(f)):
+            print(f"| `{rec['Name'].split('(')[0]}` | {rec['Calls']} | {float(rec['AverageNs']):.1f} | "
+                  f"{rec['MinNs']} | {rec['MaxNs']} | {float(rec['Percentage']):.1f} |")
 
 
 def main():
@@ -287,11 +466,14 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections", default="all",
-                    help="comma list of: head (headline only), variants, rosenbrock, rotated, "
-                         "batched, table1, fig456, paper_runs, tuning, cpu, copy (default: all "
-                         "but copy)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+                    help="comma list of: head (headline only), c1, variants, c5, c3, c4, table1, "
+                         "fig456, paper_runs, cpu, tuning, copy (default: all but tuning and copy)")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--counters", metavar="DIR", help="summarise rocprofv3 CSV output and exit")
     args = ap.parse_args()
+    if args.counters:
+        counters_summary(args.counters)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(there is no cross-GPU path)", file=sys.stderr)
@@ -302,145 +484,78 @@ def main():
     from paper_2101_06599_amd import synth
     torch.cuda.set_device(0)
     de.lib()
-    secs = set(args.sections.split(",")) if args.sections != "all" else {
-        "variants", "rosenbrock", "rotated", "batched", "table1", "fig456", "paper_runs", "tuning",
-        "cpu"}
+    allsec = {"c1", "variants", "c5", "c3", "c4", "table1", "fig456", "paper_runs", "cpu"}
+    secs = allsec if args.sections == "all" else set(args.sections.split(","))
     K, W = args.steps, args.warmup
 
     head = dict(synth.RASTRIGIN_D1000, xo="nec", dtype="fp64")
-    gpu, h = run_variant(head, K, W, prof_K=min(K, 200))
+    gpu = de.DE([head])
+    gpu.generation(W)
+    ms = time_gens(gpu, K)
+    kms = kernel_ms(gpu, max(200, K))
     win = winners(gpu, 20)
     gpu.close()
-    g_graph, h_graph = run_variant(head, K, W, prof_K=10, graph=True)
+    g_graph = de.DE([head])
+    g_graph.graph(True)
+    g_graph.generation(64)
+    ms_graph = time_gens(g_graph, 128)
     g_graph.close()
     N, D, CR = head["N"], head["D"], head["CR"]
     ab = alg_bytes("nec", N, D, CR, 8)
-    achieved = ab / (h["kernel_ms"] * 1e-3) / 1e9
-    traffic = traffic_from_profile("gen_rastrigin_nec_fp64_2048x1000")
+    achieved = ab / (kms * 1e-3) / 1e9
+    tb = traffic("c2_nec_fp64")
     out = {
         "metric": "pop*dim*gen/s (shifted Rastrigin D=1000 N=2048, NEC, FP64)",
-        "value": h["pop_dim_gen_s"], "unit": "pop*dim*gen/s", "n_gpus": 1, "steps": K,
-        "warmup": W, "ms_per_step": h["ms_per_gen"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "shifted Rastrigin, D=1000, N=2048, F=0.5, CR=0.9, "
-                               "DE/rand/1/NEC, FP64, x~U[-5.12,5.12], o~U[-4,4], Philox seed 0",
-                   "N": N, "D": D, "generation": "one generation per step",
-                   "launch": "one kernel per generation, stream-ordered"},
-        "graph_replay_ms_per_step": h_graph["ms_per_gen"],
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_generation<double, RASTRIGIN, NEC>",
-                     "kernel_ms": h["kernel_ms"], "alg_bytes_per_launch": ab,
-                     "lower_bound_bytes_per_launch": lower_bytes("nec", N, D, CR, 8, win),
-                     "winner_fraction": win},
+        "value": N * D * K / (ms / 1e3), "unit": "pop*dim*gen/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded populations and shifts)",
+        "config": {"workload": "shifted Rastrigin, D=1000, N=2048, F=0.5, CR=0.9, DE/rand/1/NEC, "
+                               "FP64, x~U[-5.12,5.12], o~U[-4,4], Philox seed 0",
+                   "N": N, "D": D, "generation": "one generation per step"},
+        "graph_replay_ms_per_step": r4(ms_graph / 128),
     }
-
-    if "variants" in secs:
-        var = {}
-        for dtype in ("fp64", "fp32"):
-            es = 8 if dtype == "fp64" else 4
-            for xo, impl in (("nec", "lane"), ("bin", "lane"), ("exp", "scan"), ("exp", "lane"),
-                             ("exp", "job")):
-                cfg = dict(synth.RASTRIGIN_D1000, xo=xo, dtype=dtype, exp_impl=impl)
-                kk = K if impl != "job" else max(10, K // 10)
-                g2, r = run_variant(cfg, kk, min(W, 10), prof_K=min(kk, 100))
-                g2.close()
-                name = f"{xo}{'' if xo != 'exp' else '-' + impl}_{dtype}"
-                byt = alg_bytes(xo, cfg["N"], cfg["D"], cfg["CR"], es)
-                r["hbm_frac_kernel"] = byt / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
-                var[name] = r
-        for dtype in ("fp64", "fp32"):
-            nec = var[f"nec_{dtype}"]["ms_per_gen"]
-            var[f"ratio_nec_over_bin_time_{dtype}"] = nec / var[f"bin_{dtype}"]["ms_per_gen"]
-            var[f"speedup_nec_vs_exp_job_{dtype}"] = var[f"exp-job_{dtype}"]["ms_per_gen"] / nec
-            var[f"speedup_nec_vs_exp_scan_{dtype}"] = var[f"exp-scan_{dtype}"]["ms_per_gen"] / nec
-        out["variants"] = var
-
-    if "rosenbrock" in secs:
-        ros = {}
-        for xo, impl in (("nec", "lane"), ("bin", "lane"), ("exp", "scan")):
-            cfg = dict(synth.ROSENBROCK_D10000, xo=xo, exp_impl=impl)
-            g2, r = run_variant(cfg, 100, 5, prof_K=50)
-            g2.close()
-            byt = alg_bytes(xo, cfg["N"], cfg["D"], cfg["CR"], 4)
-            r["hbm_frac_kernel"] = byt / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
-            r["alg_bytes_per_gen"] = byt
-            ros[xo if xo != "exp" else "exp-scan"] = r
-        out["rosenbrock_d10000_n8192_fp32"] = ros
-
-    if "rotated" in secs:
-        rot_np = synth.rotation(2048, 0)
-        rot = torch.as_tensor(rot_np, dtype=torch.float64, device="cuda:0")
-        rr = {}
-        for mm, dtype, mdt, mult in (("bf16x6", "fp32", "bf16", 6), ("bf16x3", "fp32", "bf16", 3),
-                                     ("fp32", "fp32", "fp32", 1), ("fp64", "fp64", "fp64", 1)):
-            cfg = dict(synth.ELLIPSOID_D2048, xo="nec", dtype=dtype, mm=mm, rot=rot)
-            g2, r = run_variant(cfg, 20, 2, prof_K=10)
-            g2.close()
-            flops = 2.0 * cfg["N"] * cfg["D"] ** 2
-            tf = flops / (r["kernel_ms"] * 1e-3) / 1e12
-            r.update(algorithmic_tflops=tf, executed_tflops=tf * mult,
-                     mfma_peak_tflops=MFMA_PEAK_TFLOPS[mdt],
-                     mfma_frac=tf * mult / MFMA_PEAK_TFLOPS[mdt])
-            rr[mm] = r
-        out["rotated_ellipsoid_d2048_n4096"] = rr
-
-    if "batched" in secs:
-        cfgs = synth.batch_table(512, seed=0)
-        g2 = de.DE(cfgs)
-        g2.generation(5)
-        kb = 100
-        ms = time_gens(g2, kb)
-        kms = kernel_ms(g2, 50)
-        elems = sum(c["N"] * c["D"] for c in cfgs)
-        byt = sum(alg_bytes("nec", c["N"], c["D"], c["CR"], 4) for c in cfgs)
-        g2.close()
-        # the same generations replayed from captured 64-generation graphs
-        g3 = de.DE(cfgs)
-        g3.graph(True)
-        g3.generation(64)  # capture
-        ms_graph = time_gens(g3, 128)
-        g3.close()
-        out["batched_512_runs_nec_fp32"] = {
-            "runs": 512, "elements": elems, "ms_per_gen": ms / kb, "kernel_ms": kms,
-            "pop_dim_gen_s": elems * kb / (ms / 1e3),
-            "hbm_frac_kernel": byt / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "graph_replay_ms_per_gen": ms_graph / 128}
-
     if "table1" in secs:
         out["table1_masks"] = table1(torch, de)
-
     if "fig456" in secs:
-        out["fig456_nec_vs_pexp"] = fig456(torch, de)
-
+        out["fig456_pexp_scan_vs_nec"] = fig456(torch, de)
     if "paper_runs" in secs:
-        out["paper_runs"] = paper_runs(torch, de, synth)
-
+        out["table2_runs"] = paper_runs(torch, de, synth)
     if "tuning" in secs:
         from paper_2101_06599_amd.tune import tune_tpr
-        tun = {}
-        for name, cfg in (("rastrigin_d1000_n2048_nec_fp64", head),
-                          ("rosenbrock_d10000_n8192_nec_fp32",
-                           dict(synth.ROSENBROCK_D10000, xo="nec"))):
-            best, table = tune_tpr(cfg, gens=64, use_cache=False)
-            tun[name] = {"best_tpr": best, "ms_per_gen_by_tpr": table}
-        out["tuning"] = tun
-
+        best, tab = tune_tpr(head, gens=64, use_cache=False)
+        out["tuning_headline"] = {"best_tpr": best, "ms_by_tpr": {k: r4(v) for k, v in tab.items()}}
     if "copy" in secs:
-        # counter calibration: an elementwise kernel that reads and writes a
-        # known number of bytes (b = -a over 256 MiB)
+        # counter calibration: b = -a over 256 MiB of float32 (reads and
+        # writes a known number of bytes)
         n = 256 << 20
         a = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
         for _ in range(5):
             torch.neg(a, out=b)
-        torch.cuda.synchronize()
+        sync()
         out["copy_calibration"] = {"kernel": "torch.neg over float32", "bytes_read": n,
                                    "bytes_written": n, "launches": 5}
-
+    if "c1" in secs:
+        out["c1_sphere_d10_n50"] = c1_sphere(synth)
+    if "variants" in secs:
+        out["c2_rastrigin_d1000_n2048"] = c2_variants(synth, K, W)
+    if "c4" in secs:
+        out["c4_batched_512"] = c4_batched(synth)
+    if "c3" in secs:
+        out["c3_rotated_d2048_n4096"] = c3_rotated(torch, synth)
+    if "c5" in secs:
+        out["c5_rosenbrock_d10000_n8192"] = c5_rosenbrock(synth)
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": tb,
+                       "kernel": "k_generation<double, RASTRIGIN, NEC>", "kernel_ms": r4(kms),
+                       "alg_bytes_per_launch": r4(ab), "winner_fraction": r4(win),
+                       "frac_min": r4(min_bytes("nec", N, D, CR, 8, win) / (kms * 1e-3) / 1e9
+                                      / HBM_PEAK_GBS),
+                       "frac_ctr": None if tb is None else r4(tb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS),
+                       "note": "33 MB working set: Infinity-Cache resident"}
     if "cpu" in secs:
-        out["cpu_baseline"] = cpu_baseline(head, args.cpu_seconds)
-    print(json.dumps(out))
+        out["cpu_baseline"] = cpu_baseline(synth, head, args.cpu_seconds)
+    print(json.dumps(out, separators=(",", ":")))
 
 
 if __name__ == "__main__":
