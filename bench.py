@@ -6,7 +6,9 @@ A step is one generation of the headline workload: shifted Rastrigin,
 D = 1000, N = 2048, F = 0.5, CR = 0.9, NEC crossover, FP64 (index draws,
 crossover mask, masked DE/rand/1 mutation, fitness, greedy selection and the
 best-so-far update, with the population resident in device memory).  `value`
-is pop*dim*gen/s = N * D * K / (time of K generations).
+is pop*dim*gen/s = N * D * K / (time of K generations launched one kernel at
+a time); `graph_replay_ms_per_step` gives the same generations replayed from
+captured graphs of 64.
 
 The JSON line (one line on stdout) carries, after the standard fields, the
 paper's own experiments in short form (Table 1 masks, Figs 4-6, the Table 2
@@ -229,6 +231,25 @@ def table1(torch, de, reps=100):
             "n10000_d10000_frac_write": {k: r4(1e8 / v / 1e9 / HBM_PEAK_GBS) for k, v in per.items()}}
 
 
+def masks10k(torch, de, reps=20):
+    """The 100 MB mask launch at N = D = 10^4 alone (Table 1's largest cell),
+    per crossover over the five Cr values: microseconds per launch and the
+    fraction of the HBM peak on the bytes written, and on the counter bytes
+    when they were taken on these sources."""
+    out = torch.empty((10000, 10000), dtype=torch.uint8, device="cuda:0")
+    res = {}
+    for xo in ("nec", "bin", "exp"):
+        t = sum(time_masks(torch, de, dict(N=10000, D=10000, CR=CR, xo=xo, exp_impl="scan",
+                                           fn="sphere", dtype="fp32", seed=0), out, reps)
+                for CR in (0.2, 0.4, 0.6, 0.8, 1.0)) / (5 * reps)
+        name = xo if xo != "exp" else "exp-scan"
+        tb = traffic(f"masks_{name}")
+        res[name] = {"us": r4(t * 1e6), "frac_write": r4(1e8 / t / 1e9 / HBM_PEAK_GBS),
+                     "frac_ctr": None if tb is None else r4(tb / t / 1e9 / HBM_PEAK_GBS)}
+    del out
+    return res
+
+
 def fig456(torch, de, reps=100):
     """Figs 4-6: mask time of the job-per-individual classic exponential
     crossover (p-exp) and of the wavefront-scan one over NEC, N in {100, 1000,
@@ -298,26 +319,35 @@ def c1_sphere(synth):
     return {"cols": "us per generation, pop*dim*gen/s, best after 110 generations", "runs": out}
 
 
-def c2_variants(synth, K, W):
+def c2_variants(synth, K, W, only=None):
+    """C2: the headline shape under every crossover and exp mapping, FP64 and
+    FP32 (`only`: a subset of the variant names, for counter runs in which
+    each kernel must appear under one variant)."""
     out = {}
     for dtype in ("fp64", "fp32"):
         es = 8 if dtype == "fp64" else 4
         for xo, impl in (("nec", "lane"), ("bin", "lane"), ("exp", "scan"), ("exp", "lane"),
                          ("exp", "job")):
+            name = f"{xo}{'' if xo != 'exp' else '-' + impl}_{dtype}"
+            if only is not None and name not in only:
+                continue
             cfg = dict(synth.RASTRIGIN_D1000, xo=xo, dtype=dtype, exp_impl=impl)
             kk = K if impl != "job" else max(10, K // 10)
             r = run_variant(cfg, kk, min(W, 10), prof_K=100, win_K=10)
-            name = f"{xo}{'' if xo != 'exp' else '-' + impl}_{dtype}"
             d = {"ms": r4(r["ms_per_gen"]), "kernel_ms": r4(r["kernel_ms"]),
                  "pdg_s": r4(r["pop_dim_gen_s"])}
             d.update(fracs(f"c2_{name}", xo, cfg["N"], cfg["D"], cfg["CR"], es, r["win"],
                            r["kernel_ms"]))
             out[name] = d
     for dtype in ("fp64", "fp32"):
+        if f"nec_{dtype}" not in out:
+            continue
         nec = out[f"nec_{dtype}"]["ms"]
-        out[f"nec_over_bin_time_{dtype}"] = r4(nec / out[f"bin_{dtype}"]["ms"])
-        out[f"exp-job_over_nec_time_{dtype}"] = r4(out[f"exp-job_{dtype}"]["ms"] / nec)
-        out[f"exp-scan_over_nec_time_{dtype}"] = r4(out[f"exp-scan_{dtype}"]["ms"] / nec)
+        for other, key in (("bin", "nec_over_bin_time"), ("exp-job", "exp-job_over_nec_time"),
+                           ("exp-scan", "exp-scan_over_nec_time")):
+            if f"{other}_{dtype}" in out:
+                t = out[f"{other}_{dtype}"]["ms"]
+                out[f"{key}_{dtype}"] = r4(nec / t if other == "bin" else t / nec)
     return out
 
 
@@ -352,7 +382,8 @@ def c3_rotated(torch, synth):
         tf = flops / (r["kernel_ms"] * 1e-3) / 1e12
         out[mm] = {"ms_per_gen": r4(r["ms_per_gen"]), "product_ms": r4(r["kernel_ms"]),
                    "alg_tflops": r4(tf), "exec_tflops": r4(tf * mult),
-                   "mfma_frac": r4(tf * mult / MFMA_PEAK_TFLOPS[mdt])}
+                   "mfma_frac": r4(tf * mult / MFMA_PEAK_TFLOPS[mdt]),
+                   "ctr_MB": None if traffic(f"c3_{mm}") is None else r4(traffic(f"c3_{mm}") / 1e6)}
     return out
 
 
@@ -369,7 +400,7 @@ def c4_batched(synth):
     g2.close()
     g3 = de.DE(cfgs)
     g3.graph(500)
-    g3.generation(500)  # captures the 500-generation graph, replays it once
+    g3.generation(500)  # replays the 500-generation graph captured above once
     ms_graph = time_gens(g3, 500)
     g3.close()
     byt = sum(alg_bytes("nec", c["N"], c["D"], c["CR"], 4) for c in cfgs)
@@ -460,6 +491,79 @@ def counters_summary(d):
                   f"{rec['MinNs']} | {rec['MaxNs']} | {float(rec['Percentage']):.1f} |")
 
 
+# Kernel of each traffic tag, as rocprofv3 names it (template arguments
+# <T, FN, XO, ...>: FN 1 Rastrigin, 2 Rosenbrock, -1 per run; XO 0 bin, 1 exp,
+# 2 NEC, -1 per run).  A counter run must hold each of these kernels under one
+# workload only: exp-lane and exp-scan share a kernel, so the counter runs
+# take the scan variant alone.
+TRAFFIC_KERNELS = {
+    "c2_nec_fp64": "de::k_generation<double, 1, 2,",
+    "c2_bin_fp64": "de::k_generation<double, 1, 0,",
+    "c2_exp-scan_fp64": "de::k_generation<double, 1, 1,",
+    "c2_nec_fp32": "de::k_generation<float, 1, 2,",
+    "c2_bin_fp32": "de::k_generation<float, 1, 0,",
+    "c2_exp-scan_fp32": "de::k_generation<float, 1, 1,",
+    "c5_nec": "de::k_generation_stream<float, 2, 2,",
+    "c5_bin": "de::k_generation<float, 2, 0,",
+    "c5_exp-scan": "de::k_generation_stream<float, 2, 1,",
+    "c4_batched": "de::k_generation<float, -1, -1,",
+    "c3_bf16x6": "de::k_rot_gemm_split<3,",
+    "c3_bf16x3": "de::k_rot_gemm_split<2,",
+    "c3_fp32": "de::k_rot_gemm<1>",
+    "c3_fp64": "de::k_rot_gemm<0>",
+    "masks_nec": "de::k_masks<2>",
+    "masks_bin": "de::k_masks<0>",
+    "masks_exp-scan": "de::k_masks<1>",
+}
+COPY_KERNEL = "neg_kernel"      # torch.neg of the `copy` section
+COPY_BYTES = 256 << 20          # it reads and writes this many bytes per launch
+
+
+def counter_values(dirs):
+    vals = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for rec in csv.DictReader(open(f)):
+                name = rec["Kernel_Name"]
+                name = name[5:] if name.startswith("void ") else name
+                vals.setdefault((name, rec["Counter_Name"]), []).append(float(rec["Counter_Value"]))
+    return vals
+
+
+def record_traffic(dirs):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each tagged kernel,
+    scaled by what the same counter reads for the copy kernel, written to
+    profiles/traffic.json with the hash of the sources they were taken on."""
+    vals = counter_values(dirs)
+
+    def mean(pat, ctr):
+        v = [x for (kn, cn), xs in vals.items() if cn == ctr and pat in kn for x in xs]
+        return (sum(v) / len(v) if v else None), len(v)
+
+    scale = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        kib, n = mean(COPY_KERNEL, ctr)
+        if not kib:
+            sys.exit(f"no {ctr} reading of the copy kernel under {dirs}")
+        scale[ctr] = COPY_BYTES / (kib * 1024.0)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    sha = source_sha()
+    print(f"\ncalibration (bytes per counted byte): fetch {scale['FETCH_SIZE']:.4f}, "
+          f"write {scale['WRITE_SIZE']:.4f}\n\n| tag | kernel | fetch MB | write MB | dispatches |")
+    print("|---|---|---|---|---|")
+    for tag, pat in TRAFFIC_KERNELS.items():
+        (f, nf), (w, nw) = mean(pat, "FETCH_SIZE"), mean(pat, "WRITE_SIZE")
+        if f is None or w is None:
+            continue
+        fb, wb = f * 1024.0 * scale["FETCH_SIZE"], w * 1024.0 * scale["WRITE_SIZE"]
+        rec[tag] = {"source_sha": sha, "kernel": pat, "fetch_bytes": fb, "write_bytes": wb,
+                    "bytes_per_launch": fb + wb, "dispatches": [nf, nw]}
+        print(f"| {tag} | `{pat}` | {fb / 1e6:.2f} | {wb / 1e6:.2f} | {nf}, {nw} |")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,12 +571,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections", default="all",
                     help="comma list of: head (headline only), c1, variants, c5, c3, c4, table1, "
-                         "fig456, paper_runs, cpu, tuning, copy (default: all but tuning and copy)")
+                         "masks10k, fig456, paper_runs, cpu, tuning, copy (default: all but "
+                         "masks10k, tuning and copy)")
+    ap.add_argument("--variants", default=None,
+                    help="comma list of C2 variant names to run (default: all)")
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
-    ap.add_argument("--counters", metavar="DIR", help="summarise rocprofv3 CSV output and exit")
+    ap.add_argument("--counters", metavar="DIR", nargs="+",
+                    help="summarise rocprofv3 CSV output under DIR(s) and exit")
+    ap.add_argument("--record", action="store_true",
+                    help="with --counters over a FETCH_SIZE and a WRITE_SIZE run: write "
+                         "profiles/traffic.json (calibrated by the torch.neg copy)")
     args = ap.parse_args()
     if args.counters:
-        counters_summary(args.counters)
+        for d in args.counters:
+            counters_summary(d)
+        if args.record:
+            record_traffic(args.counters)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -485,6 +599,7 @@ def main():
     torch.cuda.set_device(0)
     de.lib()
     allsec = {"c1", "variants", "c5", "c3", "c4", "table1", "fig456", "paper_runs", "cpu"}
+    # not in the default set: masks10k (a subset of table1), tuning, copy
     secs = allsec if args.sections == "all" else set(args.sections.split(","))
     K, W = args.steps, args.warmup
 
@@ -494,12 +609,10 @@ def main():
     ms = time_gens(gpu, K)
     kms = kernel_ms(gpu, max(200, K))
     win = winners(gpu, 20)
+    # the same generations replayed from a captured graph of 64 (two blocks)
+    gpu.graph(True)
+    ms_graph = time_gens(gpu, 128)
     gpu.close()
-    g_graph = de.DE([head])
-    g_graph.graph(True)
-    g_graph.generation(64)
-    ms_graph = time_gens(g_graph, 128)
-    g_graph.close()
     N, D, CR = head["N"], head["D"], head["CR"]
     ab = alg_bytes("nec", N, D, CR, 8)
     achieved = ab / (kms * 1e-3) / 1e9
@@ -516,6 +629,8 @@ def main():
     }
     if "table1" in secs:
         out["table1_masks"] = table1(torch, de)
+    if "masks10k" in secs:
+        out["masks_n10000_d10000"] = masks10k(torch, de)
     if "fig456" in secs:
         out["fig456_pexp_scan_vs_nec"] = fig456(torch, de)
     if "paper_runs" in secs:
@@ -538,7 +653,8 @@ def main():
     if "c1" in secs:
         out["c1_sphere_d10_n50"] = c1_sphere(synth)
     if "variants" in secs:
-        out["c2_rastrigin_d1000_n2048"] = c2_variants(synth, K, W)
+        only = None if args.variants is None else set(args.variants.split(","))
+        out["c2_rastrigin_d1000_n2048"] = c2_variants(synth, K, W, only)
     if "c4" in secs:
         out["c4_batched_512"] = c4_batched(synth)
     if "c3" in secs:

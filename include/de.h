@@ -257,13 +257,16 @@ de_status de_profile(de_handle* h, int32_t enable);
 de_status de_profile_read(de_handle* h, double* main_ms, int64_t* main_launches);
 
 /* Graph replay: with enable = 1, de_generation runs whole blocks of 64
- * generations (with their best-so-far update) by launching one HIP graph,
- * captured on first use, instead of launching each kernel; enable = B > 1
- * captures blocks of B generations (the best-so-far is updated after every
- * 64 of them and after the last); 0 switches graphs off.  Generations left
- * over from whole blocks are launched directly.  Results are identical either
- * way.  Ignored while kernel timing (de_profile) is on.  DE_E_INVALID for a
- * negative enable. */
+ * generations (with their best-so-far update) by launching one HIP graph
+ * instead of launching each kernel; enable = B > 1 uses blocks of B
+ * generations (the best-so-far is updated after every 64 of them and after
+ * the last); 0 switches graphs off.  The graph is captured and uploaded to
+ * the device by this call (synchronising a private stream; nothing runs on
+ * the population), so the first replay costs what later ones do.
+ * Generations left over from whole blocks are launched directly.  Results
+ * are identical either way.  Ignored while kernel timing (de_profile) is on.
+ * DE_E_INVALID for a negative enable; a failed capture returns its HIP error
+ * and leaves graphs on, to be captured again on the next call. */
 de_status de_graph(de_handle* h, int32_t enable);
 
 /* Message for the last failed call on h (or on a NULL handle); valid until

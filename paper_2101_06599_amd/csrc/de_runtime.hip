@@ -843,6 +843,15 @@ de_status de_graph(de_handle* h, int32_t enable) {
     h->gexec = nullptr;
   }
   h->graph_block = B;
+  if (B > 0 && !h->gexec) {
+    // capture and upload now, so that the first block replayed costs what
+    // every later one does (the captured kernels take their generation
+    // numbers from the device base, so the graph depends on no state here)
+    de_status st = capture_block(h);
+    if (st != DE_OK) return st;
+    HIPCHECK(h, hipGraphUpload(h->gexec, h->cap_stream));
+    HIPCHECK(h, hipStreamSynchronize(h->cap_stream));
+  }
   return DE_OK;
 }
 

@@ -124,10 +124,11 @@ __device__ __forceinline__ uint32_t build_chunk(const RunDev& P, const RowCtx<T>
   return build_chunk_from(P, R, c, load4(R.xi + 4 * c), u);
 }
 
-// Trial value of a single element j (used only past the register-cached part
-// of very long rows, for the Rosenbrock neighbour of a chunk's last element).
+// Trial value of a single element j whose parent value xj is in hand (the
+// Rosenbrock neighbour of a chunk's last element); the donors are read only
+// when the mask covers j.
 template <typename T>
-__device__ __forceinline__ T trial_elem(const RunDev& P, const RowCtx<T>& R, uint32_t j) {
+__device__ __forceinline__ T trial_from(const RunDev& P, const RowCtx<T>& R, uint32_t j, T xj) {
   bool m;
   if (R.xo == XO_BIN) {
     const uint4 b = draw(P, TAG_BIN, R.g, R.i, j >> 2);
@@ -136,7 +137,12 @@ __device__ __forceinline__ T trial_elem(const RunDev& P, const RowCtx<T>& R, uin
     const uint32_t off = j >= R.jr ? j - R.jr : j + R.D - R.jr;
     m = off < R.L;
   }
-  return m ? Math<T>::fma_(R.F, R.x1[j] - R.x2[j], R.x0[j]) : R.xi[j];
+  return m ? Math<T>::fma_(R.F, R.x1[j] - R.x2[j], R.x0[j]) : xj;
+}
+
+template <typename T>
+__device__ __forceinline__ T trial_elem(const RunDev& P, const RowCtx<T>& R, uint32_t j) {
+  return trial_from(P, R, j, R.xi[j]);
 }
 
 // Fitness contribution of one chunk; for Rosenbrock only the pairs inside the

@@ -26,6 +26,11 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
   __shared__ T red[S::RPB * S::NW];
   __shared__ uint32_t redc[S::RPB * S::NW];
   __shared__ T red2[kTwoStat<FN> ? S::RPB * S::NW : 1];
+  // Rosenbrock pairs that cross from one wavefront of a row into the next:
+  // first and last z of each wavefront's chunks (rows of several wavefronts).
+  constexpr bool kRosenEdge = (FN == FN_ROSENBROCK || FN == FN_ANY) && S::NW > 1;
+  constexpr int kEdge = kRosenEdge ? S::RPB * S::NW * MAXIT : 1;
+  __shared__ T zfirst[kEdge], zlast[kEdge];
 
   const uint32_t t = threadIdx.x % TPR;
   const uint32_t slot = threadIdx.x / TPR;
@@ -137,11 +142,17 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
                                                           : exp_length_serial(P, R.g, i);
   R.L = __builtin_amdgcn_readfirstlane(R.L);
   // Phase 2: mask, donors where the mask is set, trial and fitness terms.
-  // Rosenbrock's pair across chunks c and c + 1 is added right after chunk c:
-  // the first z of chunk c + 1 is the next lane's (a wavefront's chunks are
-  // consecutive) or, for a wavefront's last lane, computed from the element.
-  // Whether the row is Rosenbrock is wave-uniform (one run per wavefront).
+  // Rosenbrock's pair across chunks c and c + 1 is added right after chunk c
+  // when the first z of chunk c + 1 is the next lane's (a wavefront's chunks
+  // are consecutive).  A wavefront's last lane pairs with the first lane of
+  // the next wavefront of the row: through LDS after the loop, or (one
+  // wavefront per row) with lane 0's value one chunk group later, carried in
+  // a register; only the pair that leaves the cached chunks computes the
+  // neighbouring element itself.  Whether the row is Rosenbrock is
+  // wave-uniform (one run per wavefront).
   const bool rosen = FN == FN_ROSENBROCK || (FN == FN_ANY && fn == FN_ROSENBROCK);
+  T zcarry = T(0);
+  bool carry = false;
 #pragma unroll
   for (int k = 0; k < MAXIT; ++k) {
     const uint32_t c = k * TPR + t;
@@ -164,10 +175,42 @@ k_generation(const RunDev* __restrict__ runs, int32_t run_single, const uint2* _
     if constexpr (FN == FN_ROSENBROCK || FN == FN_ANY) {
       if (rosen) {
         const T znb = __shfl_down(zf, 1);
+        if constexpr (S::NW == 1) {
+          const T z0 = __shfl(zf, 0);
+          if (carry) acc += rosen_term(zcarry, z0);
+          carry = false;
+        } else if (lane == 0) {
+          zfirst[(slot * S::NW + wave) * MAXIT + k] = zf;
+        }
         if (in && 4 * c + 4 < R.D) {
-          const T zn = lane != 63 ? znb : (trial_elem(P, R, 4 * c + 4) - R.o[4 * c + 4]) + T(1);
           const T zl = (u[k][3] - os[k].v[3]) + T(1);
-          acc += rosen_term(zl, zn);
+          if (lane != 63) {
+            acc += rosen_term(zl, znb);
+          } else if (k + 1 < MAXIT && S::NW == 1) {
+            zcarry = zl;
+            carry = true;
+          } else if (k + 1 < MAXIT || wave + 1 < S::NW) {
+            if constexpr (kRosenEdge) zlast[(slot * S::NW + wave) * MAXIT + k] = zl;
+          } else {
+            acc += rosen_term(zl, (trial_elem(P, R, 4 * c + 4) - R.o[4 * c + 4]) + T(1));
+          }
+        }
+      }
+    }
+  }
+  if constexpr (kRosenEdge) {
+    // every row of the block reaches this barrier (batched rows of other
+    // functions included)
+    __syncthreads();
+    if (rosen && lane == 63) {
+#pragma unroll
+      for (int k = 0; k < MAXIT; ++k) {
+        const uint32_t c = k * TPR + t;
+        if (c < nchunk && 4 * c + 4 < R.D && (k + 1 < MAXIT || wave + 1 < S::NW)) {
+          const int nk = wave + 1 < S::NW ? k : k + 1;
+          const uint32_t nw = wave + 1 < S::NW ? wave + 1 : 0u;
+          acc += rosen_term(zlast[(slot * S::NW + wave) * MAXIT + k],
+                            zfirst[(slot * S::NW + nw) * MAXIT + nk]);
         }
       }
     }

@@ -87,11 +87,20 @@ k_generation_stream(const RunDev* __restrict__ runs, int32_t run, int64_t rows, 
   // below needs the whole wavefront).
   for (uint32_t base = 0; base < nchunk; base += U * TPR) {
     V4<T> xs[U], os[U];
+    T xn[U], on[U];  // Rosenbrock: a wavefront's last lane's next element
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t c = min(base + u * TPR + t, nchunk - 1);
       xs[u] = load4(R.xi + 4 * c);
       if (shifted) os[u] = load4(R.o + 4 * c);
+      xn[u] = on[u] = T(0);
+      if constexpr (FN == FN_ROSENBROCK) {
+        if (lane == 63) {
+          const uint32_t jn = min(4 * c + 4, R.D - 1);
+          xn[u] = R.xi[jn];
+          on[u] = R.o[jn];
+        }
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -108,10 +117,10 @@ k_generation_stream(const RunDev* __restrict__ runs, int32_t run, int64_t rows, 
       if constexpr (FN == FN_ROSENBROCK) {
         // the pair that crosses into chunk c + 1: its first z is the next
         // lane's (a wavefront's chunks are consecutive), or computed here by
-        // the wavefront's last lane
+        // the wavefront's last lane from the element loaded with its chunk
         const T znb = __shfl_down(zf, 1);
         if (in && 4 * c + 4 < R.D) {
-          const T zn = lane != 63 ? znb : (trial_elem(P, R, 4 * c + 4) - R.o[4 * c + 4]) + T(1);
+          const T zn = lane != 63 ? znb : (trial_from(P, R, 4 * c + 4, xn[u]) - on[u]) + T(1);
           const T zl = (v[3] - os[u].v[3]) + T(1);
           acc += rosen_term(zl, zn);
         }
@@ -204,8 +213,12 @@ k_generation_stream(const RunDev* __restrict__ runs, int32_t run, int64_t rows, 
 
 // ---- host-side dispatch ----------------------------------------------------
 
-// chunks per lane in flight
-constexpr int kStreamU = 4;
+// chunks per lane in flight (C5's D = 10^4 FP32 rows at 256 lanes: 2 chunks
+// 73 us per generation, 1: 77, 3: 76, 4: 81, 8: 96)
+#ifndef DE_STREAM_U
+#define DE_STREAM_U 2
+#endif
+constexpr int kStreamU = DE_STREAM_U;
 
 template <typename T, int FN, int XO, int TPR>
 static hipError_t go(const GenLaunch& L) {
