@@ -55,7 +55,7 @@ def _load() -> dict:
 
 def _store(key: str, best: int, table: dict) -> None:
     cache = _load()
-    cache[key] = {"tpr": best, "ms": {str(k): v for k, v in table.items()}}
+    cache[key] = {"best": best, "ms": {str(k): v for k, v in table.items()}}
     tmp = CACHE + ".tmp"
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1)
@@ -89,9 +89,9 @@ def tune_tpr(cfg: dict, gens: int = 64, candidates=CANDIDATES, use_cache: bool =
     """(fastest tpr, {tpr: ms per generation}) for one run description."""
     key = _key(cfg)
     cache = _load()
-    if use_cache and key in cache:
+    if use_cache and key in cache and "best" in cache[key]:
         rec = cache[key]
-        return int(rec["tpr"]), {int(k): v for k, v in rec["ms"].items()}
+        return int(rec["best"]), {int(k): v for k, v in rec["ms"].items()}
     table = {t: measure(cfg, t, gens) for t in candidates}
     best = min(table, key=table.get)
     _store(key, best, table)
@@ -103,9 +103,9 @@ def tune_batched(cfgs: list, gens: int = 32, candidates=BATCHED, use_cache: bool
     together (one width for the whole batch)."""
     key = _batch_key(cfgs)
     cache = _load()
-    if use_cache and key in cache:
+    if use_cache and key in cache and "best" in cache[key]:
         rec = cache[key]
-        return int(rec["tpr"]), {int(k): v for k, v in rec["ms"].items()}
+        return int(rec["best"]), {int(k): v for k, v in rec["ms"].items()}
     table = {t: measure(cfgs, t, gens) for t in candidates}
     best = min(table, key=table.get)
     _store(key, best, table)
@@ -135,11 +135,11 @@ def _time_gens(cfgs, gens: int, warmup: int = 2) -> float:
 def tune_rot_tile(cfg: dict, gens: int = 10, use_cache: bool = True):
     """(fastest tile, {tile: ms per generation}) for a rotated run in a
     split-bf16 mode (cfg carries its device rotation tensor `rot`)."""
-    key = _key(dict(cfg, xo="tile"))
+    key = "tile|" + _key(cfg)
     cache = _load()
-    if use_cache and key in cache:
+    if use_cache and key in cache and "best" in cache[key]:
         rec = cache[key]
-        return int(rec["tpr"]), {int(k): v for k, v in rec["ms"].items()}
+        return int(rec["best"]), {int(k): v for k, v in rec["ms"].items()}
     table = {t: _time_gens([dict(cfg, tile=t)], gens) for t in (1, 2, 3)}
     best = min(table, key=table.get)
     _store(key, best, table)

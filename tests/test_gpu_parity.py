@@ -779,6 +779,32 @@ def test_autotuned_row_width_gives_same_generations():
     assert np.all(np.abs(fa - fb) <= 1e-5 * np.abs(fa))
 
 
+def test_autotuned_batch_and_tile_paths():
+    """DE(..., tune=True) on a batched table and on a split-bf16 rotated run:
+    the tuned widths and tile shapes are valid choices and the tuned handles
+    step exactly like the handles they were tuned for."""
+    from paper_2101_06599_amd import synth
+    from paper_2101_06599_amd.tune import tune_batched, tune_rot_tile
+    cfgs = synth.batch_table(n_runs=5, seed=4, max_D=300, max_N=60)
+    best, table = tune_batched(cfgs, gens=4, use_cache=False)
+    assert best in (64, 128, 256) and set(table) == {64, 128, 256}
+    a, b = DE(cfgs), DE([dict(c, tpr=best) for c in cfgs])
+    a.generation(10)
+    b.generation(10)
+    for r in range(len(cfgs)):
+        pa, fa, _ = a.state(r)
+        pb, fb, _ = b.state(r)
+        assert np.array_equal(pa, pb)
+        assert np.all(np.abs(fa - fb) <= 1e-5 * np.abs(fa))
+    a.close()
+    b.close()
+    rot = rotation(160, 3)
+    cfg = gpu_runs([ell("bf16x6", "fp32", D=160, N=64)], rot)[0]
+    tile, ttab = tune_rot_tile(cfg, gens=2, use_cache=False)
+    assert tile in (1, 2, 3) and set(ttab) == {1, 2, 3}
+    run_parity(ell("bf16x6", "fp32", D=160, N=64, tile=tile), 2, rot=rot)
+
+
 # ---- edge cases --------------------------------------------------------------
 
 @pytest.mark.parametrize("xo,impl", [("bin", "lane"), ("exp", "scan"), ("exp", "job"),
