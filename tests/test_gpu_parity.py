@@ -716,14 +716,17 @@ def test_full_size_rastrigin_2048x1000(dtype, xo):
     sampled_rows(cfg, gens=3)
 
 
-@pytest.mark.parametrize("xo", ["nec", "bin"])
+@pytest.mark.parametrize("xo", ["nec", "bin", "exp"])
 def test_full_size_rosenbrock_8192x10000(xo):
+    """The benchmark's three D = 10^4 variants: NEC and exp-scan rows are
+    streamed, binomial rows held in registers."""
     from paper_2101_06599_amd import synth
-    cfg = dict(synth.ROSENBROCK_D10000, xo=xo)
+    cfg = dict(synth.ROSENBROCK_D10000, xo=xo, exp_impl="scan")
     sampled_rows(cfg, gens=2, n_sample=12)
 
 
-@pytest.mark.parametrize("mm,dtype", [("bf16x6", "fp32"), ("fp32", "fp32"), ("fp64", "fp64")])
+@pytest.mark.parametrize("mm,dtype", [("bf16x6", "fp32"), ("bf16x3", "fp32"), ("fp32", "fp32"),
+                                      ("fp64", "fp64")])
 def test_full_size_rotated_4096x2048(mm, dtype):
     from paper_2101_06599_amd import synth
     cfg = dict(synth.ELLIPSOID_D2048, mm=mm, dtype=dtype, xo="nec")
