@@ -25,7 +25,7 @@ struct alignas(32) BestState {
   int64_t idx;    // row of the best individual
   int64_t gen;    // generation that found it
   uint32_t g;     // generation the record is up to date with
-  uint32_t flush_done;  // blocks of the running update that are done (0 between updates)
+  uint32_t pad;
 };
 
 // Generations whose best-so-far update is deferred: every row writes its

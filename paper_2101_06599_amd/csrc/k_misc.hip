@@ -268,47 +268,46 @@ __global__ void __launch_bounds__(256) k_best_init(const RunDev* __restrict__ ru
     B->idx = m.idx;
     B->gen = run_gen(P, 0);
     B->g = run_gen(P, 0);
-    B->flush_done = 0;
   }
 }
 
-// Deferred update of the best so far, in one launch.  Block (k, run) takes the
-// minimum over the rows generation gfirst + k of that run replaced; the last
-// of the run's blocks to finish (a counter in the run's BestState, back at
-// zero afterwards) walks the generations in order, and a strictly lower
-// minimum than the best so far records that generation.  Between
-// improvements every row keeps f_i >= best, so the minimum over the replaced
-// rows decides.  No block waits for another.
-__global__ void __launch_bounds__(256) k_best_flush(const RunDev* __restrict__ runs,
-                                                    GenNo gfirst_no, int count) {
+// Deferred update, pass 1: the minimum over the rows each generation
+// replaced (block (k, run) handles generation gfirst + k of that run).
+__global__ void __launch_bounds__(256) k_best_gen_min(const RunDev* __restrict__ runs,
+                                                      GenNo gfirst) {
   const RunDev& P = runs[blockIdx.y];
-  const uint32_t gfirst = gen_value(gfirst_no);
-  const uint32_t gnew = gfirst + blockIdx.x;
+  const uint32_t gnew = gen_value(gfirst) + blockIdx.x;
   const int64_t off = static_cast<int64_t>(gnew % kHist) * P.N;
   const GenMin m = P.dtype == 0 ? block_argmin(static_cast<const double*>(P.hist) + off, P.N)
                                 : block_argmin(static_cast<const float*>(P.hist) + off, P.N);
-  if (threadIdx.x != 0) return;
-  P.mins[gnew % kHist] = m;
-  __threadfence();  // this generation's minimum is visible before it is counted
+  if (threadIdx.x == 0) P.mins[gnew % kHist] = m;
+}
+
+// Pass 2: walk the generations in order; a strictly lower minimum than the
+// best so far records that generation.  Between improvements every row keeps
+// f_i >= best, so the minimum over the replaced rows decides.
+__global__ void k_best_scan(const RunDev* __restrict__ runs, int n_runs, GenNo gfirst_no,
+                            int count) {
+  const uint32_t gfirst = gen_value(gfirst_no);
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_runs) return;
+  const RunDev& P = runs[r];
   BestState* B = P.best;
-  if (atomicAdd(&B->flush_done, 1u) != static_cast<uint32_t>(count) - 1u) return;
-  __threadfence();  // every counted minimum is visible to the walk below
   double bf = B->f;
   int64_t bi = B->idx, bg = B->gen;
   for (int k = 0; k < count; ++k) {
-    const uint32_t g = gfirst + k;
-    const GenMin mk = P.mins[g % kHist];
-    if (mk.f < bf) {
-      bf = mk.f;
-      bi = mk.idx;
-      bg = run_gen(P, g);
+    const uint32_t gnew = gfirst + k;
+    const GenMin m = P.mins[gnew % kHist];
+    if (m.f < bf) {
+      bf = m.f;
+      bi = m.idx;
+      bg = run_gen(P, gnew);
     }
   }
   B->f = bf;
   B->idx = bi;
   B->gen = bg;
   B->g = run_gen(P, gfirst + count - 1);
-  B->flush_done = 0;
 }
 
 // FP64 fitness of the best row, recomputed from the stored vector.
@@ -510,7 +509,9 @@ hipError_t launch_best_init(const RunDev* runs, int n_runs, hipStream_t s) {
 hipError_t launch_best_flush(const RunDev* runs, int n_runs, GenNo gfirst, int count,
                              hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_best_flush, dim3(count, n_runs), dim3(256), 0, s, runs, gfirst, count);
+  hipLaunchKernelGGL(k_best_gen_min, dim3(count, n_runs), dim3(256), 0, s, runs, gfirst);
+  hipLaunchKernelGGL(k_best_scan, dim3(nblk(n_runs, 256)), dim3(256), 0, s, runs, n_runs, gfirst,
+                     count);
   return hipGetLastError();
 }
 
