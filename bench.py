@@ -121,15 +121,22 @@ def sync():
 
 def time_gens(gpu, K):
     """Milliseconds for K generations (HIP events on the launch stream,
-    synchronised before and after)."""
+    synchronised before and after).  The library is called through the C ABI
+    directly, with its arguments prepared before the first event, so that the
+    Python binding's own overhead stays out of the timed span."""
+    import ctypes as C
     import torch
+    import paper_2101_06599_amd as de
     s = torch.cuda.current_stream()
+    L, h, st = de.lib(), gpu._h, C.c_void_p(s.cuda_stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(s)
-    gpu.generation(K)
+    rc = L.de_generation(h, int(K), st)
     e1.record(s)
     torch.cuda.synchronize()
+    if rc != 0:
+        raise RuntimeError(f"de_generation: {L.de_last_error(h).decode()}")
     return e0.elapsed_time(e1)
 
 
