@@ -149,12 +149,14 @@ typedef struct {
                        which the two buffers differ (exp and NEC; binomial
                        rows are always written whole).  Results do not depend
                        on it. */
-  int32_t tile;     /* split-bf16 product tile (ELLIPSOID_ROT with DE_MM_BF16X3 /
-                       DE_MM_BF16X6): 0 = the default, 1..3 = the shapes the
-                       tuner chooses among (de_rot_tiles); results do not
-                       depend on it except between the two matrix-core forms,
-                       which may round the k-sum differently.  Must be 0
-                       otherwise. */
+  int32_t tile;     /* split-bf16 product block shape (ELLIPSOID_ROT with
+                       DE_MM_BF16X3 / DE_MM_BF16X6): 0 = the default, 1..3 =
+                       three measured shapes (3 pieces: 256x128 and 128x256
+                       blocks with 16x16x32 MFMA, 256x128 with 32x32x16; 2
+                       pieces: 128x128, 128x256, 128x128 with 32x32x16), of
+                       which 0 means 1.  Results do not depend on it except
+                       between the two matrix-core forms, which may round the
+                       k-sum differently.  Must be 0 otherwise. */
   double lo, hi;    /* initial population drawn uniformly from [lo, hi]^D, lo < hi */
   double olo, ohi;  /* shift o drawn uniformly from [olo, ohi]^D when shift == NULL */
   uint64_t seed;    /* Philox key */
