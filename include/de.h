@@ -170,20 +170,26 @@ typedef struct de_handle de_handle;
 /* Bytes of device workspace that de_init needs for these runs. */
 de_status de_workspace_size(const de_run_desc* runs, int32_t n_runs, size_t* bytes);
 
-/* Validates the runs, lays out the workspace (256-byte aligned device memory
- * of at least de_workspace_size bytes), draws every initial population and
- * shift, evaluates them (generation 0) and records the best.  Runs step
- * together: each de_generation call advances all of them.  Asynchronous on
- * `stream` apart from a small host-to-device copy of the run tables. */
+/* Alg 2's set-up, before its generation loop: draws every initial population
+ * uniformly from the run's box (and the shift), evaluates it (generation 0)
+ * and records the best.  Also validates the runs and lays out the workspace
+ * (256-byte aligned device memory of at least de_workspace_size bytes).
+ * Runs step together: each de_generation call advances all of them.
+ * Asynchronous on `stream` apart from a small host-to-device copy of the run
+ * tables. */
 de_status de_init(de_handle** h, const de_run_desc* runs, int32_t n_runs, void* workspace,
                   size_t ws_bytes, void* stream);
 
-/* Runs n_gens >= 0 generations of every run.  Asynchronous. */
+/* Runs n_gens >= 0 generations of every run: Alg 2's generation loop body
+ * (index choice, crossover mask, masked mutation, evaluation and selection
+ * for all N individuals, synchronously) plus the best-so-far record.
+ * Asynchronous. */
 de_status de_generation(de_handle* h, int32_t n_gens, void* stream);
 
-/* fit_out[r] = f(X[r]) for r < rows, with the run's function, shift and dtype.
- * X: device, rows x D dense of dtype; fit_out: device, rows values of dtype.
- * Asynchronous. */
+/* Alg 2's evaluation on caller rows: fit_out[r] = f(X[r]) for r < rows, with
+ * the run's function, shift and dtype (the functions of Sec. 4 and the
+ * shifted benchmarks; see de_function).  X: device, rows x D dense of dtype;
+ * fit_out: device, rows values of dtype.  Asynchronous. */
 de_status de_evaluate(de_handle* h, int32_t run, const void* X, int64_t rows, void* fit_out,
                       void* stream);
 
