@@ -95,3 +95,20 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_tuner_cache_keys_bucket_shapes(monkeypatch, tmp_path):
+    """Shapes in the same power-of-two buckets of D and N share one cache
+    record; other dtypes, functions or crossovers do not; records round-trip
+    through the JSON cache."""
+    from paper_2101_06599_amd import tune
+    monkeypatch.setattr(tune, "_device", lambda: "gfx950-test")
+    monkeypatch.setattr(tune, "CACHE", str(tmp_path / "cache.json"))
+    assert [tune.bucket(v) for v in (1, 2, 3, 1000, 1024, 1025)] == [1, 2, 4, 1024, 1024, 2048]
+    a = dict(D=1000, N=2048, dtype="fp64", fn="rastrigin", xo="nec")
+    assert tune._key(a) == tune._key(dict(a, D=700, N=1500))
+    for k, v in (("D", 1100), ("N", 4000), ("dtype", "fp32"), ("fn", "sphere"), ("xo", "bin")):
+        assert tune._key(a) != tune._key(dict(a, **{k: v}))
+    tune._store(tune._key(a), 128, {64: 0.01, 128: 0.009})
+    best, table = tune.tune_tpr(dict(a, D=999), use_cache=True)  # served from the cache
+    assert best == 128 and table == {64: 0.01, 128: 0.009}
