@@ -362,21 +362,21 @@ def c2_variants(synth, K, W, only=None):
             cfg = dict(synth.RASTRIGIN_D1000, xo=xo, dtype=dtype, exp_impl=impl)
             kk = K if impl != "job" else max(10, K // 10)
             r = run_variant(cfg, kk, min(W, 10), prof_K=100, win_K=10)
-            d = {"ms": r4(r["ms_per_gen"]), "kernel_ms": r4(r["kernel_ms"]),
-                 "pdg_s": r4(r["pop_dim_gen_s"])}
-            d.update(fracs(f"c2_{name}", xo, cfg["N"], cfg["D"], cfg["CR"], es, r["win"],
-                           r["kernel_ms"]))
-            out[name] = d
+            f = fracs(f"c2_{name}", xo, cfg["N"], cfg["D"], cfg["CR"], es, r["win"],
+                      r["kernel_ms"])
+            out[name] = [r4(r["ms_per_gen"]), r4(r["kernel_ms"]), r4(r["pop_dim_gen_s"]),
+                         f["frac_alg"], f["frac_min"], f["frac_ctr"]]
     for dtype in ("fp64", "fp32"):
         if f"nec_{dtype}" not in out:
             continue
-        nec = out[f"nec_{dtype}"]["ms"]
+        nec = out[f"nec_{dtype}"][0]
         for other, key in (("bin", "nec_over_bin_time"), ("exp-job", "exp-job_over_nec_time"),
                            ("exp-scan", "exp-scan_over_nec_time")):
             if f"{other}_{dtype}" in out:
-                t = out[f"{other}_{dtype}"]["ms"]
+                t = out[f"{other}_{dtype}"][0]
                 out[f"{key}_{dtype}"] = r4(nec / t if other == "bin" else t / nec)
-    return out
+    return dict({"cols": "ms per generation, kernel ms, pop*dim*gen/s, frac_alg, frac_min, "
+                         "frac_ctr"}, **out)
 
 
 def c5_rosenbrock(synth):
