@@ -114,6 +114,13 @@ def fracs(tag, xo, N, D, CR, esz, win, kms):
     return {k: r4(v) for k, v in out.items()}
 
 
+def device_info(torch):
+    """What the box reports about the GPU the figures were taken on."""
+    p = torch.cuda.get_device_properties(0)
+    return {"arch": p.gcnArchName.split(":")[0], "cus": p.multi_processor_count,
+            "hbm_GiB": round(p.total_memory / 2**30), "l2_MiB": round(p.L2_cache_size / 2**20, 1)}
+
+
 def sync():
     import torch
     torch.cuda.synchronize()
@@ -721,6 +728,7 @@ def main():
                                       / HBM_PEAK_GBS),
                        "frac_ctr": None if tb is None else r4(tb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS),
                        "copy_GBps": r4(copy_gbs), "frac_of_copy": r4(achieved / copy_gbs),
+                       "device": device_info(torch),
                        "note": "33 MB working set: Infinity-Cache resident"}
     if "cpu" in secs:
         out["cpu_baseline"] = cpu_baseline(synth, head, args.cpu_seconds)
