@@ -253,25 +253,26 @@ template <> struct Math<float> {
 };
 
 // sin^2(pi z) without a library call.  r = z - rint(z) lies in [-1/2, 1/2]
-// and is exact; sin(pi r) = r * sum_k c_k (r^2)^k is the Taylor series of sine
-// with c_k = (-1)^k pi^(2k+1) / (2k+1)!, rounded to the type and summed by
-// Horner's rule through k = 10 (FP64) or k = 6 (FP32).  On the whole interval
-// the dropped terms stay below 1e-16 (1e-9) of the result and the evaluated
-// value is within 2 ulp of sin(pi r).  sin^2(pi z) = sin^2(pi r) because sine
-// changes only its sign between the two.  NaN and infinities give NaN.
+// and is exact; sin(pi r) = r * P(r^2), summed by Horner's rule.  FP64: P is
+// the degree-8 minimax polynomial of sin(pi sqrt(t)) / sqrt(t) on [0, 1/4]
+// for the relative error (a Remez fit, paper_2101_06599_amd/fit_sinpi.py;
+// approximation error 2.6e-19), so the rounding of the evaluation decides
+// the accuracy: the evaluated sin^2 stays within 2.1 ulp (20 sin^2 within
+// 2.9 ulp).  FP32: the Taylor series of sine, c_k = (-1)^k pi^(2k+1) /
+// (2k+1)!, through k = 6 (dropped terms below 1e-9).  sin^2(pi z) =
+// sin^2(pi r) because sine changes only its sign between the two.  NaN and
+// infinities give NaN.
 __device__ __forceinline__ double sinpi_sq(double z) {
   const double r = z - __builtin_rint(z);
   const double t = r * r;
-  double p = 0x1.2877020d52cf0p-31;
-  p = __builtin_fma(p, t, -0x1.8a404211f9547p-26);
-  p = __builtin_fma(p, t, 0x1.aaec32af93359p-21);
-  p = __builtin_fma(p, t, -0x1.6fadb9f155744p-16);
-  p = __builtin_fma(p, t, 0x1.e8f434d018d63p-12);
-  p = __builtin_fma(p, t, -0x1.e3074fde8871fp-8);
-  p = __builtin_fma(p, t, 0x1.50783487ee782p-4);
-  p = __builtin_fma(p, t, -0x1.32d2cce62bd86p-1);
-  p = __builtin_fma(p, t, 0x1.466bc6775aae2p+1);
-  p = __builtin_fma(p, t, -0x1.4abbce625be53p+2);
+  double p = 0x1.9d1b869195c75p-21;
+  p = __builtin_fma(p, t, -0x1.6f79770c2d50fp-16);
+  p = __builtin_fma(p, t, 0x1.e8f35e9d58319p-12);
+  p = __builtin_fma(p, t, -0x1.e3074ddd1d695p-8);
+  p = __builtin_fma(p, t, 0x1.50783485190cap-4);
+  p = __builtin_fma(p, t, -0x1.32d2cce627543p-1);
+  p = __builtin_fma(p, t, 0x1.466bc6775aa6ep+1);
+  p = __builtin_fma(p, t, -0x1.4abbce625be52p+2);
   p = __builtin_fma(p, t, 0x1.921fb54442d18p+1);
   const double sv = r * p;
   return sv * sv;
@@ -291,21 +292,19 @@ __device__ __forceinline__ float sinpi_sq(float z) {
   return sv * sv;
 }
 
-// 20 sin^2(pi z), the Rastrigin term's periodic part: the same series with
-// every coefficient multiplied by sqrt(20) (saves the final multiply).
+// 20 sin^2(pi z), the Rastrigin term's periodic part: the same polynomials
+// with every coefficient multiplied by sqrt(20) (saves the final multiply).
 __device__ __forceinline__ double sinpi_sq20(double z) {
   const double r = z - __builtin_rint(z);
   const double t = r * r;
-  double p = 0x1.4b7532d364c22p-29;
-  p = __builtin_fma(p, t, -0x1.b8c93914521bcp-24);
-  p = __builtin_fma(p, t, 0x1.dd50645e071b8p-19);
-  p = __builtin_fma(p, t, -0x1.9b13c2e21891dp-14);
-  p = __builtin_fma(p, t, 0x1.115563fac6825p-9);
-  p = __builtin_fma(p, t, -0x1.0e056bbc9d3a6p-5);
-  p = __builtin_fma(p, t, 0x1.782f347fc49e3p-2);
-  p = __builtin_fma(p, t, -0x1.5709fe17202dep+1);
-  p = __builtin_fma(p, t, 0x1.6cf3241671f24p+3);
-  p = __builtin_fma(p, t, -0x1.71c57c2da483dp+4);
+  double p = 0x1.cdde45ade783cp-19;
+  p = __builtin_fma(p, t, -0x1.9ad954d2dd022p-14);
+  p = __builtin_fma(p, t, 0x1.1154ec3d37860p-9);
+  p = __builtin_fma(p, t, -0x1.0e056a9d9acf8p-5);
+  p = __builtin_fma(p, t, 0x1.782f347c9992ep-2);
+  p = __builtin_fma(p, t, -0x1.5709fe171b213p+1);
+  p = __builtin_fma(p, t, 0x1.6cf3241671ea3p+3);
+  p = __builtin_fma(p, t, -0x1.71c57c2da483cp+4);
   p = __builtin_fma(p, t, 0x1.c196908691da7p+3);
   const double sv = r * p;
   return sv * sv;
