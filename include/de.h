@@ -153,8 +153,8 @@ typedef struct {
                        DE_MM_BF16X3 / DE_MM_BF16X6): 0 = the default, 1..3 =
                        three measured shapes (3 pieces: 256x128 and 128x256
                        blocks with 16x16x32 MFMA, 256x128 with 32x32x16; 2
-                       pieces: 128x128, 128x256, 128x128 with 32x32x16), of
-                       which 0 means 1.  Results do not depend on it except
+                       pieces: 128x256, 128x128, and 256x128 with three LDS
+                       buffers, all 16x16x32), of which 0 means 1.  Results do not depend on it except
                        between the two matrix-core forms, which may round the
                        k-sum differently.  Must be 0 otherwise. */
   double lo, hi;    /* initial population drawn uniformly from [lo, hi]^D, lo < hi */

@@ -301,14 +301,38 @@ __device__ __forceinline__ int swz(int row) {
   return (row / R128) % KC;
 }
 
+// The slices go from global memory to LDS by the LDS-DMA load: lane l's 16
+// bytes at g land at LDS byte address lds + 16 l, lds wave-uniform (in M0),
+// without passing through registers; the load counts in vmcnt.  Written as
+// asm: through the compiler builtin, every LDS read and every barrier after
+// it would wait for all DMA loads in flight, which serialises the fetch of
+// the next slice with the products of this one.  It has no output register;
+// the kernel orders it with explicit vmcnt waits before the barrier that
+// publishes a slice.  One wait state separates the M0 write from the load
+// that reads it (the compiler keeps the same distance for the builtin).  M0
+// has no other user in the kernels that call it.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void lds_dma16(const void* g, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// s_waitcnt immediate for vmcnt(n), the other counters left alone
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
 // Split-bf16 product, one BM x BN tile of Z per block of (BM/64) x (BN/64)
 // waves, each wave a 64x64 sub-tile as MF x MF matrix-core tiles (MF = 16:
 // 16x16x32, MF = 32: 32x32x16).  The A pieces come from the piece planes of
 // the rows (apc), the B pieces from the split M.  K advances KT columns per
-// step through two LDS buffers: the next slice goes into registers at the
-// start of a step and into the other buffer at its end, one barrier apart.
+// step through NBUF LDS buffers with NBUF - 1 slices in flight: at the start
+// of step kt a wave waits for its own loads of slice kt, a barrier makes all
+// of slice kt visible (and ends every read of slice kt - 1), and the wave
+// then starts the loads of slice kt + NBUF - 1 into the buffer slice kt - 1
+// held before computing on slice kt.
 // What the split product reads of a run, passed by value (kernel arguments
-// rather than loads from the run record keep the staged slices in registers).
+// rather than loads from the run record keep the addresses in registers).
 struct SplitArgs {
   const __bf16* apc;   // A pieces: plane p, row i at apc + (p N + i) ldk
   const __bf16* B[3];  // M pieces, rows padded to a multiple of 256, pitch ldk
@@ -318,16 +342,20 @@ struct SplitArgs {
   int32_t ntile;
 };
 
-template <int P, int BM, int BN, int KT, int MF>
+template <int P, int BM, int BN, int KT, int MF, int NBUF>
 __global__ void __launch_bounds__((BM / 64) * (BN / 64) * 64)
 k_rot_gemm_split(SplitArgs Pr, int64_t rows) {
-  constexpr int WNV = BN / 64, NT = (BM / 64) * WNV * 64;
-  constexpr int KC = KT / 8;                       // 16-byte chunks per slice row
-  constexpr int AU = BM * KC / NT, BU = BN * KC / NT;  // chunks per thread and piece
-  static_assert(AU * NT == BM * KC && BU * NT == BN * KC, "whole chunks per thread");
+  constexpr int WNV = BN / 64, NT = (BM / 64) * WNV * 64, WAVES = NT / 64;
+  constexpr int KC = KT / 8;  // 16-byte chunks per slice row
+  // a piece's slice is BM * KC (BN * KC) chunks = ABLK (BBLK) blocks of 64
+  // chunks, one DMA load of a wave each; wave w loads blocks w, w + WAVES, ...
+  constexpr int ABLK = BM * KC / 64, BBLK = BN * KC / 64;
+  static_assert(ABLK % WAVES == 0 && BBLK % WAVES == 0, "whole blocks per wave");
+  constexpr int NA = ABLK / WAVES, NB = BBLK / WAVES, LPS = P * (NA + NB);
   static_assert(MF == 32 ? KT % 16 == 0 : KT % 32 == 0, "k steps of the matrix-core form");
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][P][BM * KT];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][P][BN * KT];
+  static_assert(NBUF >= 2 && LPS * (NBUF - 2) < 64, "vmcnt range");
+  __shared__ __attribute__((aligned(16))) __bf16 As[NBUF][P][BM * KT];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NBUF][P][BN * KT];
   __shared__ float red[WNV][BM];
 
   const int64_t D = Pr.D, ldk = Pr.ldk;
@@ -338,47 +366,43 @@ k_rot_gemm_split(SplitArgs Pr, int64_t rows) {
   if (nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;  // a contiguous range of tiles per XCD
   const int tm = b / ntn, tn = b % ntn;
   const int64_t row0 = static_cast<int64_t>(tm) * BM, col0 = static_cast<int64_t>(tn) * BN;
-  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int wm = wave / WNV, wn = wave % WNV;
 
-  // thread t moves chunks u = t + j NT of every piece: row u / KC, chunk u % KC
+  // lane l of block blk fills chunk u = 64 blk + l of the slice: row u / KC,
+  // stored chunk u % KC, which holds logical chunk (u % KC) ^ swz(row)
   const __bf16* apc = Pr.apc;
   const int64_t plane = Pr.N * ldk;
-  int64_t oa[AU], ob[BU];
-  int la[AU], lb[BU];
+  int64_t oa[NA], ob[NB];
 #pragma unroll
-  for (int j = 0; j < AU; ++j) {
-    const int u = tid + j * NT, r = u / KC, kc = u % KC;
+  for (int j = 0; j < NA; ++j) {
+    const int u = (wave + j * WAVES) * 64 + lane, r = u / KC, kc = (u % KC) ^ swz<KT>(r);
     oa[j] = min(row0 + r, rows - 1) * ldk + kc * 8;
-    la[j] = r * KT + (kc ^ swz<KT>(r)) * 8;
   }
 #pragma unroll
-  for (int j = 0; j < BU; ++j) {
-    const int u = tid + j * NT, r = u / KC, kc = u % KC;
+  for (int j = 0; j < NB; ++j) {
+    const int u = (wave + j * WAVES) * 64 + lane, r = u / KC, kc = (u % KC) ^ swz<KT>(r);
     ob[j] = (col0 + r) * ldk + kc * 8;  // rows of the M pieces are padded to a multiple of 256
-    lb[j] = r * KT + (kc ^ swz<KT>(r)) * 8;
   }
-  uint4 va[P][AU], vb[P][BU];
-#define DE_SPLIT_FETCH(K0)                                                                    \
-  do {                                                                                        \
-    const int64_t k0_ = (K0);                                                                 \
-    _Pragma("unroll") for (int p = 0; p < P; ++p) {                                          \
-      _Pragma("unroll") for (int j = 0; j < AU; ++j)                                         \
-        va[p][j] = *reinterpret_cast<const uint4*>(apc + p * plane + oa[j] + k0_);            \
-      _Pragma("unroll") for (int j = 0; j < BU; ++j)                                         \
-        vb[p][j] = *reinterpret_cast<const uint4*>(Pr.B[p] + ob[j] + k0_);                    \
-    }                                                                                         \
-  } while (0)
-#define DE_SPLIT_STASH(BUF)                                                                   \
-  do {                                                                                        \
-    const int b_ = (BUF);                                                                     \
-    _Pragma("unroll") for (int p = 0; p < P; ++p) {                                          \
-      _Pragma("unroll") for (int j = 0; j < AU; ++j)                                         \
-        *reinterpret_cast<uint4*>(&As[b_][p][la[j]]) = va[p][j];                              \
-      _Pragma("unroll") for (int j = 0; j < BU; ++j)                                         \
-        *reinterpret_cast<uint4*>(&Bs[b_][p][lb[j]]) = vb[p][j];                              \
-    }                                                                                         \
-  } while (0)
+  const uint32_t lds_a = __builtin_amdgcn_readfirstlane(
+      static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) void*)&As[0][0][0])));
+  const uint32_t lds_b = __builtin_amdgcn_readfirstlane(
+      static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) void*)&Bs[0][0][0])));
+  auto fetch = [&](int slice, int buf) {
+    const int64_t k0 = static_cast<int64_t>(slice) * KT;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+#pragma unroll
+      for (int j = 0; j < NA; ++j)
+        lds_dma16(apc + p * plane + oa[j] + k0,
+                  lds_a + 2u * static_cast<uint32_t>((buf * P + p) * BM * KT + (wave + j * WAVES) * 512));
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        lds_dma16(Pr.B[p] + ob[j] + k0,
+                  lds_b + 2u * static_cast<uint32_t>((buf * P + p) * BN * KT + (wave + j * WAVES) * 512));
+    }
+  };
 
   constexpr int NPR = P == 3 ? 6 : 3;
   constexpr int SM = 64 / MF;  // matrix-core tiles per wave side
@@ -390,14 +414,16 @@ k_rot_gemm_split(SplitArgs Pr, int64_t rows) {
     for (int n = 0; n < SM; ++n) acc[m][n] = Acc{};
 
   const int nk = static_cast<int>((D + KT - 1) / KT);
-  DE_SPLIT_FETCH(0);
-  DE_SPLIT_STASH(0);
-  __syncthreads();
+#pragma unroll
+  for (int sl = 0; sl < NBUF - 1; ++sl)
+    if (sl < nk) fetch(sl, sl);
   for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    // Fetched and stored on every step (the last one re-fetches its own slice
-    // into the unused buffer): no branch around them keeps va, vb in registers.
-    DE_SPLIT_FETCH(static_cast<int64_t>(kt + 1 < nk ? kt + 1 : kt) * KT);
+    // slice kt landed once at most the NBUF - 2 slices after it are in flight
+    if (kt + NBUF - 2 < nk) __builtin_amdgcn_s_waitcnt(vmcnt_imm(LPS * (NBUF - 2)));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    __syncthreads();
+    if (kt + NBUF - 1 < nk) fetch(kt + NBUF - 1, (kt + NBUF - 1) % NBUF);
+    const int buf = kt % NBUF;
     constexpr int KS = MF == 32 ? 16 : 32;  // k per matrix-core op
 #pragma unroll
     for (int ks = 0; ks < KT / KS; ++ks) {
@@ -428,11 +454,8 @@ k_rot_gemm_split(SplitArgs Pr, int64_t rows) {
           }
       });
     }
-    DE_SPLIT_STASH(buf ^ 1);
-    __syncthreads();
   }
-#undef DE_SPLIT_FETCH
-#undef DE_SPLIT_STASH
+  // the last step waited for vmcnt(0): no load is in flight past here
 
   // ---- epilogue: sum_n w_n z_in^2 over this block's columns ----
   constexpr int NR = MF == 32 ? 16 : 4;  // accumulator registers per tile
@@ -594,22 +617,23 @@ hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s) {
 }
 
 // Tile shapes of the split-bf16 product (BM x BN block tile, KT, matrix-core
-// form MF) for P pieces: option 1 is the default, 2 and 3 the runners-up of a
-// sweep on MI355X at 4096 x 2048 x 2048 (rows, D, D); the tuner picks among
-// them per shape.
+// form MF, NBUF LDS buffers) for P pieces: option 1 is the default, 2 and 3
+// the runners-up, from sweeps on MI355X at 4096 x 2048 x 2048 (rows, D, D) in
+// a harness and in place behind the trial kernel; the tuner picks among them
+// per shape.
 template <int P, int OPT> struct SplitShape;
-template <> struct SplitShape<3, 1> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 16; };
-template <> struct SplitShape<3, 2> { static constexpr int BM = 128, BN = 256, KT = 32, MF = 16; };
-template <> struct SplitShape<3, 3> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 32; };
-template <> struct SplitShape<2, 1> { static constexpr int BM = 128, BN = 128, KT = 32, MF = 16; };
-template <> struct SplitShape<2, 2> { static constexpr int BM = 128, BN = 256, KT = 32, MF = 16; };
-template <> struct SplitShape<2, 3> { static constexpr int BM = 128, BN = 128, KT = 32, MF = 32; };
+template <> struct SplitShape<3, 1> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 16, NBUF = 2; };
+template <> struct SplitShape<3, 2> { static constexpr int BM = 128, BN = 256, KT = 32, MF = 16, NBUF = 2; };
+template <> struct SplitShape<3, 3> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 32, NBUF = 2; };
+template <> struct SplitShape<2, 1> { static constexpr int BM = 128, BN = 256, KT = 32, MF = 16, NBUF = 2; };
+template <> struct SplitShape<2, 2> { static constexpr int BM = 128, BN = 128, KT = 32, MF = 16, NBUF = 2; };
+template <> struct SplitShape<2, 3> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 16, NBUF = 3; };
 
 template <int P, int OPT>
 static void launch_split_gemm(const SplitArgs& a, int64_t rows, hipStream_t s) {
   using S = SplitShape<P, OPT>;
   const int64_t blocks = ((rows + S::BM - 1) / S::BM) * ((a.D + S::BN - 1) / S::BN);
-  hipLaunchKernelGGL((k_rot_gemm_split<P, S::BM, S::BN, S::KT, S::MF>), dim3(blocks),
+  hipLaunchKernelGGL((k_rot_gemm_split<P, S::BM, S::BN, S::KT, S::MF, S::NBUF>), dim3(blocks),
                      dim3((S::BM / 64) * (S::BN / 64) * 64), 0, s, a, rows);
 }
 
