@@ -152,11 +152,11 @@ typedef struct {
   int32_t tile;     /* split-bf16 product block shape (ELLIPSOID_ROT with
                        DE_MM_BF16X3 / DE_MM_BF16X6): 0 = the default, 1..3 =
                        three measured shapes (3 pieces: 256x128 and 128x256
-                       blocks with 16x16x32 MFMA, 256x128 with 32x32x16; 2
-                       pieces: 128x256, 128x128, and 256x128 with three LDS
-                       buffers, all 16x16x32), of which 0 means 1.  Results do not depend on it except
-                       between the two matrix-core forms, which may round the
-                       k-sum differently.  Must be 0 otherwise. */
+                       blocks in two alternating wave groups, 256x128 in one;
+                       2 pieces: 128x256 in two groups, 128x128, 256x128 in
+                       two groups), of which 0 means 1.  All use the 16x16x32
+                       matrix-core form and the same k order, so results do
+                       not depend on it.  Must be 0 otherwise. */
   double lo, hi;    /* initial population drawn uniformly from [lo, hi]^D, lo < hi */
   double olo, ohi;  /* shift o drawn uniformly from [olo, ohi]^D when shift == NULL */
   uint64_t seed;    /* Philox key */

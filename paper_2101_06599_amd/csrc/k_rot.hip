@@ -302,7 +302,8 @@ __device__ __forceinline__ int swz(int row) {
 }
 
 // The slices go from global memory to LDS by the LDS-DMA load: lane l's 16
-// bytes at g land at LDS byte address lds + 16 l, lds wave-uniform (in M0),
+// bytes at base + off land at LDS byte address lds + 16 l (base and lds
+// wave-uniform, lds in M0, off a per-lane byte offset),
 // without passing through registers; the load counts in vmcnt.  Written as
 // asm: through the compiler builtin, every LDS read and every barrier after
 // it would wait for all DMA loads in flight, which serialises the fetch of
@@ -313,8 +314,8 @@ __device__ __forceinline__ int swz(int row) {
 // has no other user in the kernels that call it.
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm"
-__device__ __forceinline__ void lds_dma16(const void* g, uint32_t lds) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds)
+__device__ __forceinline__ void lds_dma16(const void* base, uint32_t off, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(off), "s"(base), "s"(lds)
                : "memory", "m0");
 }
 #pragma clang diagnostic pop
@@ -326,11 +327,20 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) |
 // waves, each wave a 64x64 sub-tile as MF x MF matrix-core tiles (MF = 16:
 // 16x16x32, MF = 32: 32x32x16).  The A pieces come from the piece planes of
 // the rows (apc), the B pieces from the split M.  K advances KT columns per
-// step through NBUF LDS buffers with NBUF - 1 slices in flight: at the start
-// of step kt a wave waits for its own loads of slice kt, a barrier makes all
-// of slice kt visible (and ends every read of slice kt - 1), and the wave
-// then starts the loads of slice kt + NBUF - 1 into the buffer slice kt - 1
-// held before computing on slice kt.
+// step through NBUF LDS buffers.
+//   Without PP, every wave loads its share of the slices, NBUF - 1 slices in
+// flight: at the start of step kt a wave waits for its own loads of slice kt,
+// a barrier makes all of slice kt visible (and ends every read of slice
+// kt - 1), and the wave then starts the loads of slice kt + NBUF - 1 into the
+// buffer slice kt - 1 held before computing on slice kt.
+//   With PP (8 waves, two buffers) the waves form two groups of four, one
+// wave of each per SIMD, half a step apart: every wave runs "read the
+// fragments of slice k | barrier | products of slice k | barrier", group 1
+// one barrier behind group 0, so that on each SIMD one wave issues
+// matrix-core ops while the other reads LDS; the product phase runs at raised
+// wave priority.  Group 0 loads all of slice k + 1 when it starts reading
+// slice k (both groups are done with slice k - 1, whose buffer it refills)
+// and waits for it at the end of its products of slice k.
 // What the split product reads of a run, passed by value (kernel arguments
 // rather than loads from the run record keep the addresses in registers).
 struct SplitArgs {
@@ -342,16 +352,19 @@ struct SplitArgs {
   int32_t ntile;
 };
 
-template <int P, int BM, int BN, int KT, int MF, int NBUF>
+template <int P, int BM, int BN, int KT, int MF, int NBUF, bool PP>
 __global__ void __launch_bounds__((BM / 64) * (BN / 64) * 64)
 k_rot_gemm_split(SplitArgs Pr, int64_t rows) {
   constexpr int WNV = BN / 64, NT = (BM / 64) * WNV * 64, WAVES = NT / 64;
   constexpr int KC = KT / 8;  // 16-byte chunks per slice row
+  static_assert(!PP || (WAVES == 8 && NBUF == 2), "ping-pong: 8 waves, two buffers");
   // a piece's slice is BM * KC (BN * KC) chunks = ABLK (BBLK) blocks of 64
-  // chunks, one DMA load of a wave each; wave w loads blocks w, w + WAVES, ...
+  // chunks, one DMA load of a wave each; loading wave w loads blocks w,
+  // w + LW, ...
+  constexpr int LW = PP ? WAVES / 2 : WAVES;
   constexpr int ABLK = BM * KC / 64, BBLK = BN * KC / 64;
-  static_assert(ABLK % WAVES == 0 && BBLK % WAVES == 0, "whole blocks per wave");
-  constexpr int NA = ABLK / WAVES, NB = BBLK / WAVES, LPS = P * (NA + NB);
+  static_assert(ABLK % LW == 0 && BBLK % LW == 0, "whole blocks per loading wave");
+  constexpr int NA = ABLK / LW, NB = BBLK / LW, LPS = P * (NA + NB);
   static_assert(MF == 32 ? KT % 16 == 0 : KT % 32 == 0, "k steps of the matrix-core form");
   static_assert(NBUF >= 2 && LPS * (NBUF - 2) < 64, "vmcnt range");
   __shared__ __attribute__((aligned(16))) __bf16 As[NBUF][P][BM * KT];
@@ -369,22 +382,27 @@ k_rot_gemm_split(SplitArgs Pr, int64_t rows) {
   const int tid = threadIdx.x, lane = tid % 64;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int wm = wave / WNV, wn = wave % WNV;
+  const bool g1 = PP && wave >= LW;
+  const int lw = wave % LW;
 
   // lane l of block blk fills chunk u = 64 blk + l of the slice: row u / KC,
-  // stored chunk u % KC, which holds logical chunk (u % KC) ^ swz(row)
-  const __bf16* apc = Pr.apc;
-  const int64_t plane = Pr.N * ldk;
-  int64_t oa[NA], ob[NB];
+  // stored chunk u % KC, which holds logical chunk (u % KC) ^ swz(row).  Byte
+  // offsets from the tile's first row (< BM ldk 2 bytes; rows past the end
+  // re-read the last row).
+  uint32_t oa[NA], ob[NB];
 #pragma unroll
   for (int j = 0; j < NA; ++j) {
-    const int u = (wave + j * WAVES) * 64 + lane, r = u / KC, kc = (u % KC) ^ swz<KT>(r);
-    oa[j] = min(row0 + r, rows - 1) * ldk + kc * 8;
+    const int u = (lw + j * LW) * 64 + lane, r = u / KC, kc = (u % KC) ^ swz<KT>(r);
+    const int64_t rr = min(row0 + r, rows - 1) - row0;
+    oa[j] = static_cast<uint32_t>((rr * ldk + kc * 8) * 2);
   }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const int u = (wave + j * WAVES) * 64 + lane, r = u / KC, kc = (u % KC) ^ swz<KT>(r);
-    ob[j] = (col0 + r) * ldk + kc * 8;  // rows of the M pieces are padded to a multiple of 256
+    const int u = (lw + j * LW) * 64 + lane, r = u / KC, kc = (u % KC) ^ swz<KT>(r);
+    ob[j] = static_cast<uint32_t>((static_cast<int64_t>(r) * ldk + kc * 8) * 2);  // M rows padded to 256
   }
+  const __bf16* abase = Pr.apc + row0 * ldk;
+  const int64_t plane = Pr.N * ldk;
   const uint32_t lds_a = __builtin_amdgcn_readfirstlane(
       static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) void*)&As[0][0][0])));
   const uint32_t lds_b = __builtin_amdgcn_readfirstlane(
@@ -393,66 +411,98 @@ k_rot_gemm_split(SplitArgs Pr, int64_t rows) {
     const int64_t k0 = static_cast<int64_t>(slice) * KT;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
+      const __bf16* pa = abase + p * plane + k0;
+      const __bf16* pb = Pr.B[p] + col0 * ldk + k0;
 #pragma unroll
       for (int j = 0; j < NA; ++j)
-        lds_dma16(apc + p * plane + oa[j] + k0,
-                  lds_a + 2u * static_cast<uint32_t>((buf * P + p) * BM * KT + (wave + j * WAVES) * 512));
+        lds_dma16(pa, oa[j], lds_a + 2u * static_cast<uint32_t>((buf * P + p) * BM * KT + (lw + j * LW) * 512));
 #pragma unroll
       for (int j = 0; j < NB; ++j)
-        lds_dma16(Pr.B[p] + ob[j] + k0,
-                  lds_b + 2u * static_cast<uint32_t>((buf * P + p) * BN * KT + (wave + j * WAVES) * 512));
+        lds_dma16(pb, ob[j], lds_b + 2u * static_cast<uint32_t>((buf * P + p) * BN * KT + (lw + j * LW) * 512));
     }
   };
 
   constexpr int NPR = P == 3 ? 6 : 3;
-  constexpr int SM = 64 / MF;  // matrix-core tiles per wave side
+  constexpr int SM = 64 / MF;             // matrix-core tiles per wave side
+  constexpr int KS = MF == 32 ? 16 : 32;  // k per matrix-core op
   using Acc = typename std::conditional<MF == 32, f32x16, f32x4>::type;
   Acc acc[SM][SM];
 #pragma unroll
   for (int m = 0; m < SM; ++m)
 #pragma unroll
     for (int n = 0; n < SM; ++n) acc[m][n] = Acc{};
+  bf16x8 fa[P][SM], fb[P][SM];
+  auto read_fragments = [&](int buf, int ks) {
+    const int kc = ks * (KS / 8) + lane / MF;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int m = 0; m < SM; ++m) {
+        const int ra = wm * 64 + m * MF + lane % MF;
+        const int rb = wn * 64 + m * MF + lane % MF;
+        fa[p][m] = *reinterpret_cast<const bf16x8*>(&As[buf][p][ra * KT + (kc ^ swz<KT>(ra)) * 8]);
+        fb[p][m] = *reinterpret_cast<const bf16x8*>(&Bs[buf][p][rb * KT + (kc ^ swz<KT>(rb)) * 8]);
+      }
+  };
+  // the product loop is outermost, so consecutive matrix-core ops use
+  // different accumulators
+  auto products = [&]() {
+    static_for<NPR>([&](auto qc) {
+      constexpr int ia = SplitProd<P, decltype(qc)::value>::a;
+      constexpr int ib = SplitProd<P, decltype(qc)::value>::b;
+#pragma unroll
+      for (int m = 0; m < SM; ++m)
+#pragma unroll
+        for (int n = 0; n < SM; ++n) {
+          if constexpr (MF == 32)
+            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[ia][m], fb[ib][n], acc[m][n], 0, 0, 0);
+          else
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[ia][m], fb[ib][n], acc[m][n], 0, 0, 0);
+        }
+    });
+  };
 
   const int nk = static_cast<int>((D + KT - 1) / KT);
-#pragma unroll
-  for (int sl = 0; sl < NBUF - 1; ++sl)
-    if (sl < nk) fetch(sl, sl);
-  for (int kt = 0; kt < nk; ++kt) {
-    // slice kt landed once at most the NBUF - 2 slices after it are in flight
-    if (kt + NBUF - 2 < nk) __builtin_amdgcn_s_waitcnt(vmcnt_imm(LPS * (NBUF - 2)));
-    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+  if constexpr (PP) {
+    static_assert(KT == KS, "one fragment set per step");
+    if (!g1) {
+      fetch(0, 0);
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    }
     __syncthreads();
-    if (kt + NBUF - 1 < nk) fetch(kt + NBUF - 1, (kt + NBUF - 1) % NBUF);
-    const int buf = kt % NBUF;
-    constexpr int KS = MF == 32 ? 16 : 32;  // k per matrix-core op
+    if (g1) __syncthreads();
+    // sched_barrier(0) keeps the compiler from moving matrix-core ops across
+    // the barriers, which would undo the phases
+    for (int k = 0; k < nk; ++k) {
+      if (!g1 && k + 1 < nk) fetch(k + 1, (k + 1) & 1);
+      read_fragments(k & 1, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_setprio(1);
+      products();
+      __builtin_amdgcn_s_setprio(0);
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      __builtin_amdgcn_sched_barrier(0);
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (!g1) __syncthreads();
+  } else {
 #pragma unroll
-    for (int ks = 0; ks < KT / KS; ++ks) {
-      bf16x8 fa[P][SM], fb[P][SM];
+    for (int sl = 0; sl < NBUF - 1; ++sl)
+      if (sl < nk) fetch(sl, sl);
+    for (int kt = 0; kt < nk; ++kt) {
+      // slice kt landed once at most the NBUF - 2 slices after it are in flight
+      if (kt + NBUF - 2 < nk) __builtin_amdgcn_s_waitcnt(vmcnt_imm(LPS * (NBUF - 2)));
+      else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      __syncthreads();
+      if (kt + NBUF - 1 < nk) fetch(kt + NBUF - 1, (kt + NBUF - 1) % NBUF);
 #pragma unroll
-      for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int m = 0; m < SM; ++m) {
-          const int ra = wm * 64 + m * MF + lane % MF;
-          const int rb = wn * 64 + m * MF + lane % MF;
-          const int kc = ks * (KS / 8) + lane / MF;
-          fa[p][m] = *reinterpret_cast<const bf16x8*>(&As[buf][p][ra * KT + (kc ^ swz<KT>(ra)) * 8]);
-          fb[p][m] = *reinterpret_cast<const bf16x8*>(&Bs[buf][p][rb * KT + (kc ^ swz<KT>(rb)) * 8]);
-        }
-      // the product loop is outermost, so consecutive matrix-core ops use
-      // different accumulators
-      static_for<NPR>([&](auto qc) {
-        constexpr int ia = SplitProd<P, decltype(qc)::value>::a;
-        constexpr int ib = SplitProd<P, decltype(qc)::value>::b;
-#pragma unroll
-        for (int m = 0; m < SM; ++m)
-#pragma unroll
-          for (int n = 0; n < SM; ++n) {
-            if constexpr (MF == 32)
-              acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[ia][m], fb[ib][n], acc[m][n], 0, 0, 0);
-            else
-              acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[ia][m], fb[ib][n], acc[m][n], 0, 0, 0);
-          }
-      });
+      for (int ks = 0; ks < KT / KS; ++ks) {
+        read_fragments(kt % NBUF, ks);
+        products();
+      }
     }
   }
   // the last step waited for vmcnt(0): no load is in flight past here
@@ -617,23 +667,23 @@ hipError_t launch_prepare_rot(const RunDev& h, hipStream_t s) {
 }
 
 // Tile shapes of the split-bf16 product (BM x BN block tile, KT, matrix-core
-// form MF, NBUF LDS buffers) for P pieces: option 1 is the default, 2 and 3
+// form MF, NBUF LDS buffers, ping-pong wave groups PP) for P pieces: option 1 is the default, 2 and 3
 // the runners-up, from sweeps on MI355X at 4096 x 2048 x 2048 (rows, D, D) in
 // a harness and in place behind the trial kernel; the tuner picks among them
 // per shape.
 template <int P, int OPT> struct SplitShape;
-template <> struct SplitShape<3, 1> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 16, NBUF = 2; };
-template <> struct SplitShape<3, 2> { static constexpr int BM = 128, BN = 256, KT = 32, MF = 16, NBUF = 2; };
-template <> struct SplitShape<3, 3> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 32, NBUF = 2; };
-template <> struct SplitShape<2, 1> { static constexpr int BM = 128, BN = 256, KT = 32, MF = 16, NBUF = 2; };
-template <> struct SplitShape<2, 2> { static constexpr int BM = 128, BN = 128, KT = 32, MF = 16, NBUF = 2; };
-template <> struct SplitShape<2, 3> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 16, NBUF = 3; };
+template <> struct SplitShape<3, 1> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 16, NBUF = 2; static constexpr bool PP = true; };
+template <> struct SplitShape<3, 2> { static constexpr int BM = 128, BN = 256, KT = 32, MF = 16, NBUF = 2; static constexpr bool PP = true; };
+template <> struct SplitShape<3, 3> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 16, NBUF = 2; static constexpr bool PP = false; };
+template <> struct SplitShape<2, 1> { static constexpr int BM = 128, BN = 256, KT = 32, MF = 16, NBUF = 2; static constexpr bool PP = true; };
+template <> struct SplitShape<2, 2> { static constexpr int BM = 128, BN = 128, KT = 32, MF = 16, NBUF = 2; static constexpr bool PP = false; };
+template <> struct SplitShape<2, 3> { static constexpr int BM = 256, BN = 128, KT = 32, MF = 16, NBUF = 2; static constexpr bool PP = true; };
 
 template <int P, int OPT>
 static void launch_split_gemm(const SplitArgs& a, int64_t rows, hipStream_t s) {
   using S = SplitShape<P, OPT>;
   const int64_t blocks = ((rows + S::BM - 1) / S::BM) * ((a.D + S::BN - 1) / S::BN);
-  hipLaunchKernelGGL((k_rot_gemm_split<P, S::BM, S::BN, S::KT, S::MF, S::NBUF>), dim3(blocks),
+  hipLaunchKernelGGL((k_rot_gemm_split<P, S::BM, S::BN, S::KT, S::MF, S::NBUF, S::PP>), dim3(blocks),
                      dim3((S::BM / 64) * (S::BN / 64) * 64), 0, s, a, rows);
 }
 

@@ -414,20 +414,20 @@ def test_rotated_ellipsoid(mm, dtype, xo):
 @pytest.mark.parametrize("mm", ["bf16x6", "bf16x3"])
 def test_rotated_tiles(mm, tile):
     """Every tile shape of the split-bf16 product at a D that is ragged against
-    128- and 256-wide tiles; shapes 1 and 2 use the same matrix-core form, so
-    their fitness values agree bit for bit."""
+    128- and 256-wide tiles; all shapes use the same matrix-core form and k
+    order, so their fitness values agree bit for bit."""
     D = 300
     rot = rotation(D, 6)
     run_parity(ell(mm, "fp32", D=D, N=100, tile=tile), 3, rot=rot)
-    if tile == 2:
+    if tile == 3:
         outs = []
-        for t in (1, 2):
+        for t in (1, 2, 3):
             gpu = DE([ell(mm, "fp32", D=D, N=100, tile=t)], rot)
             tr = gpu.trace(0)
             gpu.generation(2)
             outs.append(tr["ftrial"].cpu().numpy().copy())
             gpu.close()
-        assert np.array_equal(outs[0], outs[1])
+        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
 @pytest.mark.parametrize("mm", ["fp32", "bf16x6"])
