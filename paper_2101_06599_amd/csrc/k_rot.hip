@@ -303,9 +303,8 @@ __device__ __forceinline__ int swz(int row) {
 
 // The slices go from global memory to LDS by the LDS-DMA load: lane l's 16
 // bytes at base + off land at LDS byte address lds + 16 l (base and lds
-// wave-uniform, lds in M0, off a per-lane byte offset),
-// without passing through registers; the load counts in vmcnt.  Written as
-// asm: through the compiler builtin, every LDS read and every barrier after
+// wave-uniform, lds in M0, off a per-lane byte offset) without passing
+// through registers; the load counts in vmcnt.  Written as asm: through the compiler builtin, every LDS read and every barrier after
 // it would wait for all DMA loads in flight, which serialises the fetch of
 // the next slice with the products of this one.  It has no output register;
 // the kernel orders it with explicit vmcnt waits before the barrier that

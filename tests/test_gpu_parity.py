@@ -412,17 +412,18 @@ def test_rotated_ellipsoid(mm, dtype, xo):
 
 @pytest.mark.parametrize("tile", [1, 2, 3])
 @pytest.mark.parametrize("mm", ["bf16x6", "bf16x3"])
-def test_rotated_tiles(mm, tile):
-    """Every tile shape of the split-bf16 product at a D that is ragged against
-    128- and 256-wide tiles; all shapes use the same matrix-core form and k
-    order, so their fitness values agree bit for bit."""
-    D = 300
+@pytest.mark.parametrize("N,D", [(100, 300), (300, 200)])
+def test_rotated_tiles(mm, tile, N, D):
+    """Every tile shape of the split-bf16 product at shapes ragged against
+    the tiles: D against 128- and 256-wide columns and the 32-wide k slices,
+    N below one tile of rows or a tile and a part; all shapes use the same
+    matrix-core form and k order, so their fitness values agree bit for bit."""
     rot = rotation(D, 6)
-    run_parity(ell(mm, "fp32", D=D, N=100, tile=tile), 3, rot=rot)
+    run_parity(ell(mm, "fp32", D=D, N=N, tile=tile), 3, rot=rot)
     if tile == 3:
         outs = []
         for t in (1, 2, 3):
-            gpu = DE([ell(mm, "fp32", D=D, N=100, tile=t)], rot)
+            gpu = DE([ell(mm, "fp32", D=D, N=N, tile=t)], rot)
             tr = gpu.trace(0)
             gpu.generation(2)
             outs.append(tr["ftrial"].cpu().numpy().copy())
