@@ -35,10 +35,10 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 template <int MODE> struct MM;
 template <> struct MM<MM_FP64> {
-  using T = double; using L = double; static constexpr int P = 1, KT = 16, BM = 64, BN = 64, PAD = 2;
+  using T = double; using L = double; static constexpr int P = 1, KT = 16, BM = 64, BN = 64, PAD = 1;
 };
 template <> struct MM<MM_FP32> {
-  using T = float; using L = float; static constexpr int P = 1, KT = 32, BM = 128, BN = 128, PAD = 4;
+  using T = float; using L = float; static constexpr int P = 1, KT = 32, BM = 128, BN = 128, PAD = 2;
 };
 
 int rot_tile_n() { return 128; }  // BN of the FP32 and bf16 modes; FP64 uses 64
@@ -153,7 +153,14 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   static_assert(AV * E == A_SEG && BV * E == B_SEG, "whole 16-byte segments");
   uint4 va[AV], vo[AV], vb[BV];
   auto ld16 = [](const void* p) { return *reinterpret_cast<const uint4*>(p); };
-  auto st16 = [](void* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; };
+  // LDS rows are KT + PAD elements = 136 bytes, an odd multiple of 8: the 16
+  // rows one fragment read touches at a given k fall into distinct banks
+  // (with 144-byte rows a third of the LDS cycles were bank conflicts).  The
+  // rows are 8-byte aligned, so a 16-byte segment goes in as two stores.
+  auto st16 = [](void* p, uint4 v) {
+    reinterpret_cast<uint2*>(p)[0] = make_uint2(v.x, v.y);
+    reinterpret_cast<uint2*>(p)[1] = make_uint2(v.z, v.w);
+  };
 #define DE_ROT_FETCH(K0)                                                                  \
   do {                                                                                    \
     const int64_t k0_ = (K0);                                                             \
