@@ -412,7 +412,7 @@ def c3_rotated(torch, synth):
     for mm, dtype, mdt, mult in (("bf16x6", "fp32", "bf16", 6), ("bf16x3", "fp32", "bf16", 3),
                                  ("fp32", "fp32", "fp32", 1), ("fp64", "fp64", "fp64", 1)):
         cfg = dict(synth.ELLIPSOID_D2048, xo="nec", dtype=dtype, mm=mm, rot=rot)
-        r = run_variant(cfg, 20, 2, prof_K=10, best_calls=3)
+        r = run_variant(cfg, 20, 2, prof_K=30, best_calls=3)
         flops = 2.0 * cfg["N"] * cfg["D"] ** 2
         tf = flops / (r["kernel_ms"] * 1e-3) / 1e12
         out[mm] = {"ms_per_gen": r4(r["ms_per_gen"]), "product_ms": r4(r["kernel_ms"]),
