@@ -124,11 +124,23 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   const int ntm = static_cast<int>((rows + BM - 1) / BM);
   const int ntn = static_cast<int>((D + BN - 1) / BN);
   // XCD-aware order: consecutive blocks go round-robin over the 8 XCDs, so
-  // hand each XCD a contiguous range of tiles (tiles of one row block share A).
+  // hand each XCD whole rows of tiles (tiles of one row block share A) and
+  // visit them column by column, so that the blocks in flight on an XCD
+  // cover a squarer patch of Z and fetch fewer operand rows from beyond its
+  // L2 (the FP64 product: 0.69-0.70 vs 0.71-0.72 ms with row-major order);
+  // else a contiguous range of tiles per XCD.
   const int nb = ntm * ntn;
   int b = blockIdx.x;
-  if (nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
-  const int tm = b / ntn, tn = b % ntn;
+  int tm = b / ntn, tn = b % ntn;
+  if (nb % 8 == 0 && (nb / 8) % ntn == 0) {
+    const int rx = nb / 8 / ntn, x = b % 8, loc = b / 8;
+    tm = x * rx + loc % rx;
+    tn = loc / rx;
+  } else if (nb % 8 == 0) {
+    b = (b % 8) * (nb / 8) + b / 8;
+    tm = b / ntn;
+    tn = b % ntn;
+  }
   const int64_t row0 = static_cast<int64_t>(tm) * BM, col0 = static_cast<int64_t>(tn) * BN;
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
