@@ -35,10 +35,10 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 template <int MODE> struct MM;
 template <> struct MM<MM_FP64> {
-  using T = double; using L = double; static constexpr int P = 1, KT = 16, BM = 64, BN = 64, PAD = 1;
+  using T = double; using L = double; static constexpr int P = 1, KT = 16, BM = 64, BN = 64, PAD = 1, NW = 8;
 };
 template <> struct MM<MM_FP32> {
-  using T = float; using L = float; static constexpr int P = 1, KT = 32, BM = 128, BN = 128, PAD = 2;
+  using T = float; using L = float; static constexpr int P = 1, KT = 32, BM = 128, BN = 128, PAD = 2, NW = 4;
 };
 
 int rot_tile_n() { return 128; }  // BN of the FP32 and bf16 modes; FP64 uses 64
@@ -102,19 +102,23 @@ __global__ void __launch_bounds__(256) k_rot_split(const RunDev* __restrict__ ru
   if constexpr (P == 3) *reinterpret_cast<uint4*>(out + 2 * plane) = make_uint4(l[0], l[1], l[2], l[3]);
 }
 
-// FP32 / FP64 product, one 128x128 (FP64: 64x64) tile of Z per block, with
-// the shift subtracted as the A slice goes into LDS.  The next K slice is
-// fetched into registers while the matrix cores work on the current one from
-// LDS, then written into the other LDS buffer, so one barrier per K step
-// separates the two.
+// FP32 / FP64 product, one 128x128 (FP64: 64x64) tile of Z per block of NW
+// waves (NW/2 along rows, 2 along columns), with the shift subtracted as the
+// A slice goes into LDS.  The next K slice is fetched into registers while
+// the matrix cores work on the current one from LDS, then written into the
+// other LDS buffer, so one barrier per K step separates the two.  FP64 uses 8
+// waves of 16x32 (57 registers, up to 8 waves per SIMD: 0.61 vs 0.70 ms with
+// 4 waves of 32x32, the same results bit for bit); FP32 4 waves of 64x64 (8
+// waves measured the same).
 template <int MODE>
-__global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ runs, int32_t run,
-                                                 int src, GenNo ghn, int64_t rows) {
+__global__ void __launch_bounds__(64 * MM<MODE>::NW) k_rot_gemm(const RunDev* __restrict__ runs, int32_t run,
+                                                               int src, GenNo ghn, int64_t rows) {
   const uint32_t gh = gen_value(ghn);
   using C = MM<MODE>;
   using T = typename C::T;
   constexpr int BM = C::BM, BN = C::BN, KT = C::KT, LDK = KT + C::PAD;
-  constexpr int WM = BM / 32, WN = BN / 32;  // 16x16 subtiles per wave (2x2 waves)
+  constexpr int NT = 64 * C::NW, WVM = C::NW / 2;   // threads; waves along rows
+  constexpr int WM = BM / (16 * WVM), WN = BN / 32;  // 16x16 subtiles per wave
   __shared__ __attribute__((aligned(16))) T As[2][BM][LDK];
   __shared__ __attribute__((aligned(16))) T Bs[2][BN][LDK];
   __shared__ T red[2][BM];
@@ -127,8 +131,8 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   // hand each XCD whole rows of tiles (tiles of one row block share A) and
   // visit them column by column, so that the blocks in flight on an XCD
   // cover a squarer patch of Z and fetch fewer operand rows from beyond its
-  // L2 (the FP64 product: 0.69-0.70 vs 0.71-0.72 ms with row-major order);
-  // else a contiguous range of tiles per XCD.
+  // L2 (the FP64 product with 4 waves per block: 0.69-0.70 vs 0.71-0.72 ms
+  // with row-major order); else a contiguous range of tiles per XCD.
   const int nb = ntm * ntn;
   int b = blockIdx.x;
   int tm = b / ntn, tn = b % ntn;
@@ -147,9 +151,9 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
   const int wm = wave / 2, wn = wave % 2;
 
   // Global -> LDS assignment: each thread moves one row segment of the A and
-  // of the B slice (A_SEG, B_SEG contiguous values; 32 bytes or more).
-  constexpr int A_TPR = 256 / BM, A_SEG = KT / A_TPR;
-  constexpr int B_TPR = 256 / BN, B_SEG = KT / B_TPR;
+  // of the B slice (A_SEG, B_SEG contiguous values; 16 bytes or more).
+  constexpr int A_TPR = NT / BM, A_SEG = KT / A_TPR;
+  constexpr int B_TPR = NT / BN, B_SEG = KT / B_TPR;
   const int a_r = tid / A_TPR, a_k = (tid % A_TPR) * A_SEG;
   const int b_r = tid / B_TPR, b_k = (tid % B_TPR) * B_SEG;
   const int64_t ai = min(row0 + a_r, rows - 1);
@@ -220,7 +224,7 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
     for (int s = 0; s < KT / 4; ++s) {
       T af[WM], bf[WN];
 #pragma unroll
-      for (int m = 0; m < WM; ++m) af[m] = As[buf][wm * (BM / 2) + m * 16 + lane % 16][4 * s + lane / 16];
+      for (int m = 0; m < WM; ++m) af[m] = As[buf][wm * (BM / WVM) + m * 16 + lane % 16][4 * s + lane / 16];
 #pragma unroll
       for (int n = 0; n < WN; ++n) bf[n] = Bs[buf][wn * (BN / 2) + n * 16 + lane % 16][4 * s + lane / 16];
 #pragma unroll
@@ -277,13 +281,13 @@ __global__ void __launch_bounds__(256) k_rot_gemm(const RunDev* __restrict__ run
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rr = MODE == MM_FP64 ? 4 * r + lane / 16 : (lane / 16) * 4 + r;
-        red[wn][wm * (BM / 2) + m * 16 + rr] = rs[m][r];
+        red[wn][wm * (BM / WVM) + m * 16 + rr] = rs[m][r];
       }
   }
   __syncthreads();
   T* part = static_cast<T*>(Pr.part);
   const int ntot = Pr.ntile;
-  for (int rr = tid; rr < BM; rr += 256) {
+  for (int rr = tid; rr < BM; rr += NT) {
     const int64_t i = row0 + rr;
     if (i < rows) part[i * ntot + tn] = red[0][rr] + red[1][rr];
   }
@@ -742,8 +746,12 @@ static hipError_t gemm(const RunDev* runs, const RunDev& h, int run, int src, Ge
   const int bm = tile_m_of(h.mm), bn = tile_n_of(h.mm);
   const int64_t blocks = ((rows + bm - 1) / bm) * ((h.D + bn - 1) / bn);
   switch (h.mm) {
-    case MM_FP64: hipLaunchKernelGGL(k_rot_gemm<MM_FP64>, dim3(blocks), dim3(256), 0, s, runs, run, src, gh, rows); break;
-    case MM_FP32: hipLaunchKernelGGL(k_rot_gemm<MM_FP32>, dim3(blocks), dim3(256), 0, s, runs, run, src, gh, rows); break;
+    case MM_FP64:
+      hipLaunchKernelGGL(k_rot_gemm<MM_FP64>, dim3(blocks), dim3(64 * MM<MM_FP64>::NW), 0, s, runs, run, src, gh, rows);
+      break;
+    case MM_FP32:
+      hipLaunchKernelGGL(k_rot_gemm<MM_FP32>, dim3(blocks), dim3(64 * MM<MM_FP32>::NW), 0, s, runs, run, src, gh, rows);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
