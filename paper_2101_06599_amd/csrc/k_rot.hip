@@ -327,13 +327,14 @@ __device__ __forceinline__ int swz(int row) {
 // The slices go from global memory to LDS by the LDS-DMA load: lane l's 16
 // bytes at base + off land at LDS byte address lds + 16 l (base and lds
 // wave-uniform, lds in M0, off a per-lane byte offset) without passing
-// through registers; the load counts in vmcnt.  Written as asm: through the compiler builtin, every LDS read and every barrier after
-// it would wait for all DMA loads in flight, which serialises the fetch of
-// the next slice with the products of this one.  It has no output register;
-// the kernel orders it with explicit vmcnt waits before the barrier that
-// publishes a slice.  One wait state separates the M0 write from the load
-// that reads it (the compiler keeps the same distance for the builtin).  M0
-// has no other user in the kernels that call it.
+// through registers; the load counts in vmcnt.  Written as asm: through the
+// compiler builtin, every LDS read and every barrier after it would wait for
+// all DMA loads in flight, which serialises the fetch of the next slice with
+// the products of this one.  It has no output register; the kernel orders it
+// with explicit vmcnt waits before the barrier that publishes a slice.  One
+// wait state separates the M0 write from the load that reads it (the
+// compiler keeps the same distance for the builtin).  M0 has no other user in
+// the kernels that call it.
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm"
 __device__ __forceinline__ void lds_dma16(const void* base, uint32_t off, uint32_t lds) {
