@@ -431,6 +431,17 @@ def test_rotated_tiles(mm, tile, N, D):
         assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("mm,dtype", [("fp64", "fp64"), ("fp32", "fp32"), ("bf16x6", "fp32"),
+                                      ("bf16x3", "fp32")])
+@pytest.mark.parametrize("D", [2, 20, 33])
+def test_rotated_small_d(mm, dtype, D):
+    """Rotated runs whose D is below one K slice of the product (16 or 32
+    columns) or one past it, with fewer rows than one tile: the padding of the
+    operands and the partial last slice."""
+    rot = rotation(D, 8)
+    run_parity(ell(mm, dtype, D=D, N=12), 3, rot=rot)
+
+
 @pytest.mark.parametrize("mm", ["fp32", "bf16x6"])
 def test_rotated_ellipsoid_exp_job(mm):
     rot = rotation(96, 1)
