@@ -98,7 +98,8 @@ def fit_err(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     same_inf = np.isinf(a) & np.isinf(b) & (np.sign(a) == np.sign(b))
-    return np.where(same_inf, 0.0, np.abs(a - b))
+    with np.errstate(invalid="ignore"):  # inf - inf where same_inf picks 0
+        return np.where(same_inf, 0.0, np.abs(a - b))
 
 
 def _first_diff(a, b, what):
